@@ -1,0 +1,150 @@
+"""Pins for the oracle's weighted (unrolled) BP and its hand-written adjoint:
+unit weights reproduce plain min-sum BP, and the reverse-mode gradient agrees
+with FP64 central differences and with torch autograd of an independent
+unrolled implementation."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+S_PRIOR = 2.0 ** 60
+
+
+def _setup(orc, N, K, F, seed, snr=1.5):
+    code = orc.construct(N, K, 2.5)
+    msg = synth.message_bits(seed, F, K)
+    _, x = orc.encode(code, msg)
+    return code, synth.awgn_llr(x, snr, K, seed=seed)
+
+
+def test_unit_weights_are_plain_bp(orc):
+    code, llr = _setup(orc, 256, 128, 6, 1)
+    T = 7
+    w = np.ones((T, 8, 2, 256))
+    out = orc.wbp_forward(code, llr, w, orc.WbpParams(fp32=True))
+    for f in range(6):
+        L, R = orc.bp_run(llr[f], code.frozen, T, fp32=True)
+        info = code.info_idx
+        np.testing.assert_array_equal(out[f, info], L[8, info])
+        assert np.array_equal(out[f, info] < 0, (L[8, info] + R[8, info]) < 0)
+
+
+def test_unit_weights_lastk_match_decoder(orc):
+    code, llr = _setup(orc, 256, 128, 4, 2)
+    T = 9
+    w = np.ones((T, 8, 2, 256))
+    out = orc.wbp_forward(code, llr, w, orc.WbpParams(pp_mode=orc.PP_LASTK, k=3, T_ev=4, Q=4,
+                                                      seed=3, fp32=True))
+    r = orc.decode(code, llr, orc.DecodeParams(max_iter=T, stop=orc.STOP_NONE,
+                                               pp_mode=orc.PP_LASTK, k=3, T=4, Q=4, seed=3),
+                   soft=True)
+    info = code.info_idx
+    np.testing.assert_array_equal(out[:, info], r.soft_u[:, info])
+
+
+def _loss(orc, code, llr, w, p, g):
+    return float((orc.wbp_forward(code, llr, w, p) * g).sum())
+
+
+@pytest.mark.parametrize("T,pp", [(2, False), (3, False), (3, True)])
+def test_gradient_central_differences(orc, T, pp):
+    N, n = 16, 4
+    code, llr = _setup(orc, N, 8, 3, 4 + T)
+    rng = np.random.default_rng(T)
+    w = rng.uniform(0.6, 1.4, (T, n, 2, N))
+    g = rng.normal(size=(3, N))
+    g[:, code.frozen.astype(bool)] = 0.0       # loss only on information positions
+    p = (orc.WbpParams(pp_mode=orc.PP_LASTK, k=2, T_ev=1, Q=2, seed=5) if pp
+         else orc.WbpParams())
+    gw, gl = orc.wbp_backward(code, llr, w, p, g, want_llr_grad=True)
+    h = 1e-6
+    idx = rng.choice(w.size, 60, replace=False)
+    flat = w.reshape(-1)
+    for i in idx:
+        wp = flat.copy(); wp[i] += h
+        wm = flat.copy(); wm[i] -= h
+        fd = (_loss(orc, code, llr, wp.reshape(w.shape), p, g)
+              - _loss(orc, code, llr, wm.reshape(w.shape), p, g)) / (2 * h)
+        assert gw.reshape(-1)[i] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+    # weights of the last R sweep never reach the output
+    assert np.all(gw[T - 1, :, 1] == 0.0)
+
+
+def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
+    """Independent unrolled weighted min-sum BP in torch (float64), rows vectorised."""
+    F, N = llr.shape
+    T, n = w.shape[0], w.shape[1]
+    prior = torch.where(torch.as_tensor(frozen.astype(bool)), torch.tensor(S_PRIOR, dtype=torch.float64),
+                        torch.tensor(0.0, dtype=torch.float64))
+
+    def ms(x, y):
+        sx = torch.where(torch.signbit(x), -1.0, 1.0)
+        sy = torch.where(torch.signbit(y), -1.0, 1.0)
+        return torch.where(x.abs() <= y.abs(), sy * x, sx * y)
+
+    R = [torch.zeros(F, N, dtype=torch.float64) for _ in range(n + 1)]
+    R[n] = prior.expand(F, N)
+    Lc = torch.as_tensor(llr, dtype=torch.float64)
+    qcur = 0
+    for t in range(T):
+        q = (t // T_ev) % len(pool_orders) if pool_orders is not None else 0
+        if t > 0 and q != qcur:
+            for lev in range(n - k + 1, n):
+                R[lev] = torch.zeros(F, N, dtype=torch.float64)
+        qcur = q
+        order = pool_orders[q] if pool_orders is not None else list(range(n))
+        L = [Lc] + [None] * n
+        for s in range(1, n + 1):
+            b = int(order[s - 1])
+            top = torch.tensor([j for j in range(N) if not (j >> b) & 1])
+            bot = top | (1 << b)
+            l1, l2 = L[s - 1][:, top], L[s - 1][:, bot]
+            r1, r2 = R[s][:, top], R[s][:, bot]
+            out = torch.zeros(F, N, dtype=torch.float64)
+            out = out.index_put((torch.arange(F)[:, None], top[None, :]),
+                                w[t, s - 1, 0, top] * ms(l1, l2 + r2))
+            out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
+                                w[t, s - 1, 0, bot] * ms(r1, l1) + l2)
+            L[s] = out
+        if t == T - 1:
+            return L[n] + R[n]
+        newR = [None] * (n + 1)
+        newR[n] = R[n]
+        for s in range(n, 0, -1):
+            b = int(order[s - 1])
+            top = torch.tensor([j for j in range(N) if not (j >> b) & 1])
+            bot = top | (1 << b)
+            l1, l2 = L[s - 1][:, top], L[s - 1][:, bot]
+            r1, r2 = newR[s][:, top], newR[s][:, bot]
+            out = torch.zeros(F, N, dtype=torch.float64)
+            out = out.index_put((torch.arange(F)[:, None], top[None, :]),
+                                w[t, s - 1, 1, top] * ms(r1, l2 + r2))
+            out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
+                                w[t, s - 1, 1, bot] * ms(r1, l1) + r2)
+            newR[s - 1] = out
+        R = newR
+
+
+@pytest.mark.parametrize("N,T,pp", [(16, 3, False), (32, 4, True), (64, 3, False)])
+def test_gradient_matches_torch_autograd(orc, N, T, pp):
+    n = N.bit_length() - 1
+    code, llr = _setup(orc, N, N // 2, 4, 20 + N)
+    rng = np.random.default_rng(N)
+    w = rng.uniform(0.6, 1.4, (T, n, 2, N))
+    g = rng.normal(size=(4, N))
+    g[:, code.frozen.astype(bool)] = 0.0
+    if pp:
+        p = orc.WbpParams(pp_mode=orc.PP_LASTK, k=3, T_ev=2, Q=3, seed=9)
+        pool = orc.trellis_pool(n, 3, 3, seed=9)
+        k, tev = 3, 2
+    else:
+        p = orc.WbpParams()
+        pool, k, tev = None, 0, 1
+    wt = torch.tensor(w, dtype=torch.float64, requires_grad=True)
+    out = _torch_wbp(llr, code.frozen, wt, pool, k, tev)
+    ref_out = orc.wbp_forward(code, llr, w, p)
+    np.testing.assert_allclose(out.detach().numpy(), ref_out, rtol=1e-12, atol=0)
+    (out * torch.as_tensor(g)).sum().backward()
+    gw, _ = orc.wbp_backward(code, llr, w, p, g)
+    np.testing.assert_allclose(gw, wt.grad.numpy(), rtol=1e-10, atol=1e-10)
