@@ -1,0 +1,199 @@
+/*
+ * polarbp.h -- C ABI of the MI355X (gfx950) library for partially permuted
+ * multi-trellis belief-propagation decoding of CRC-aided polar codes
+ * (Ranasinghe, Rajatheva, Latva-aho, "Partially Permuted Multi-Trellis Belief
+ * Propagation for Polar Codes", arXiv 1911.08868).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named d_* are device pointers on the device that was current
+ *    when the code object was constructed; every other pointer is host memory.
+ *    The caller owns all buffers; the library neither frees nor retains them
+ *    beyond the work it enqueues.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Work is enqueued asynchronously; device faults surface at the caller's
+ *    next synchronisation.
+ *  - Return value: 0 on success, otherwise a negative code (PC_E*).  The
+ *    thread-local string polar_last_error() describes the last failure.  No
+ *    C++ exception crosses this interface.
+ *  - F = 0 frames is a no-op that returns 0.
+ *  - Factor graph: level 1 holds the channel LLRs L_{1,j} and level n+1 the
+ *    a-priori values R_{n+1,j} (Sec. II-B); stage s (1..n) joins levels s and
+ *    s+1 and, in the original graph, pairs rows 2^(s-1) apart, so stages 1..m
+ *    form N/2^m disjoint subgraphs (Sec. III).  LLR > 0 favours bit 0; the hard
+ *    decision is 0 iff R + L >= 0 (Sec. II-B).
+ */
+#ifndef POLARBP_H
+#define POLARBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PC_OK 0
+#define PC_EINVAL (-1)  /* bad argument: null pointer, size or parameter out of range */
+#define PC_ENOTSUP (-2) /* valid combination that this build does not implement       */
+#define PC_EHIP (-3)    /* HIP runtime or launch error                                */
+#define PC_ENOMEM (-4)  /* workspace too small or device allocation failed            */
+
+#define PC_STOP_NONE 0 /* run max_iter iterations                                     */
+#define PC_STOP_G 1    /* stop when u_hat G_N equals the hard decision on level 1     */
+#define PC_STOP_CRC 2  /* stop when the CRC of the decided message matches (Sec. IV)  */
+
+#define PC_PP_NONE (-1) /* standard BP on the original graph                          */
+#define PC_PP_LASTK 0   /* last k stages re-ordered from a seeded pool every T iters  */
+#define PC_PP_FULL 1    /* all n stages re-ordered: multi-trellis BP with full
+                           permutations (Sec. II-D); only L_1 and R_{n+1} survive     */
+#define PC_PP_ALG1 2    /* Algorithm 1's random subgraph per event: not implemented
+                           on the GPU (returns PC_ENOTSUP)                            */
+
+/* Opaque polar code: frozen set, CRC, and device copies of the per-row
+ * tables the decoder reads.  Immutable after construction; may be shared by
+ * threads and streams.                                                      */
+typedef struct pc_code pc_code;
+
+/* Decoder iteration parameters (Algorithm 1 inputs N_it,max and stopID, plus
+ * the min-sum scale and the first iteration at which the stop test is
+ * applied, Sec. IV).                                                        */
+typedef struct {
+    int32_t max_iter; /* N_it,max >= 1                                       */
+    float alpha;      /* min-sum scale; 1 = the unscaled min-sum of Sec. IV  */
+    int32_t stop;     /* PC_STOP_*                                           */
+    int32_t it_min;   /* stop test applied from this iteration on (>= 1)     */
+} pc_bp_params;
+
+/* Multi-trellis schedule (Sec. II-D, Sec. III).  For PC_PP_LASTK the pool
+ * holds min(pool_Q, k!) stage orders: entry 0 is the original graph, entries
+ * 1.. give stages n-k+1..n distinct non-identity orders of bits n-k..n-1,
+ * drawn from `seed` with SplitMix64 (polar_trellis_pool).  After iteration
+ * T, 2T, ... (and before max_iter) a frame that has not stopped switches to
+ * entry (iter / T) mod Q and, if its graph changed, its messages on the levels
+ * strictly inside the permuted range are reset to 0.  PC_PP_FULL is the same
+ * with k = n.                                                               */
+typedef struct {
+    int32_t mode;     /* PC_PP_*                                             */
+    int32_t k;        /* permuted stages, 2 <= k <= n (LASTK)                */
+    int32_t period_T; /* iterations between permutations, >= 1               */
+    int32_t pool_Q;   /* pool size, 1 <= Q <= 8                              */
+    int32_t P_range, P_level, D, N_min, first_reset; /* ALG1 (unsupported)   */
+    uint64_t seed;
+} pc_pp_params;
+
+/* Launch configuration picked by the autotuner; NULL selects the library's
+ * table.  rho: log2 rows held per thread per level (2 or 3); slots: frames
+ * resident per workgroup; grid: workgroups (0 = as many as fit the GPU).    */
+typedef struct {
+    int32_t rho;
+    int32_t slots;
+    int32_t grid;
+} pc_launch_cfg;
+
+/* Code construction by Bhattacharyya parameters (Sec. II-A): the K most
+ * reliable bit channels of the factor graph above, designed for BPSK-AWGN at
+ * design_ebn0_db with rate K/N (CRC included in K, Sec. IV).  N a power of
+ * two in [2, 4096]; crc_width 0 or 1..32 with crc_width < K; crc_poly the
+ * generator with or without its x^width term (MSB-first, init 0, no
+ * reflection, no final xor).  The information set carries the K - crc_width
+ * message bits first and the CRC (MSB first) last, in ascending index order.
+ * *out receives a new code owned by the caller (free with polar_code_free). */
+int polar_construct(int32_t N, int32_t K, int32_t crc_width, uint32_t crc_poly,
+                    double design_ebn0_db, pc_code **out);
+
+/* Frees a code.  No work using it may still be in flight.  NULL is a no-op. */
+int polar_code_free(pc_code *code);
+
+/* Host copies of the information set (ascending, K entries) and the frozen
+ * indicator (N bytes, 1 = frozen).  Either pointer may be NULL.             */
+int polar_code_query(const pc_code *code, int32_t *info_idx, uint8_t *frozen);
+
+/* The stage orders of the multi-trellis pool for (n, k, Q, seed):
+ * orders[q*n + s-1] is the bit used by stage s in pool entry q.  Returns the
+ * number of entries (min(Q, k!)) or a negative code.  Host only.            */
+int polar_trellis_pool(int32_t n, int32_t k, int32_t Q, uint64_t seed, int8_t *orders);
+
+/* Encoding x = u G_N, G_N = F^{(x)n} (Eq. 1): message + CRC placed on the
+ * information set, zeros on the frozen set.  d_msg uint8 [F][K - crc_width]
+ * (bit values 0/1), d_x uint8 [F][N].                                       */
+int polar_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
+                 void *stream);
+
+/* Standard min-sum BP decoding (Sec. II-B) of F frames.
+ * d_llr float [F][N] channel LLRs (4-byte aligned, finite for defined
+ * results); d_msg_hat uint8 [F][K - crc_width] decided message bits;
+ * d_iters int32 [F] iterations run (the one that met the stop test counts),
+ * or NULL; d_ok uint8 [F] verdict of the stop test on the final decisions
+ * (for PC_STOP_NONE: the CRC if the code has one, else the G test), or NULL. */
+int bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
+              uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok, void *stream);
+
+/* Partially permuted multi-trellis BP (Algorithm 1 with the fixed schedules
+ * of pc_pp_params).  Arguments as bp_decode.                                */
+int pp_mt_bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
+                    const pc_pp_params *pp, uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok,
+                    void *stream);
+
+/* pp_mt_bp_decode with two extras: d_soft_u float [F][N] (or NULL) receives
+ * the L messages on level n+1 after the final L sweep (the u-side soft output
+ * before the prior is added), and cfg (or NULL) overrides the launch
+ * configuration.                                                            */
+int pp_mt_bp_decode_ex(const pc_code *code, const float *d_llr, int64_t F,
+                       const pc_bp_params *bp, const pc_pp_params *pp, uint8_t *d_msg_hat,
+                       int32_t *d_iters, uint8_t *d_ok, float *d_soft_u,
+                       const pc_launch_cfg *cfg, void *stream);
+
+/* Batched decoding of frames of mixed length and rate in one persistent
+ * launch fed from a device work queue.  codes[0..n_codes) are codes built on
+ * this device (n_codes <= 32, all with the same crc_width, N in [64, 1024]);
+ * d_code_id int32 [F] selects each frame's code; d_llr_off int64 [F] is the
+ * float offset of frame f's N LLRs in d_llr_pool; d_bits_off int64 [F] the
+ * byte offset of its K - crc_width decided bits in d_bits_pool.  Frames are
+ * taken from the queue in the order of d_order (int32 [F], a permutation of
+ * 0..F-1, or NULL for 0..F-1).  d_iters, d_ok int32/uint8 [F] or NULL.
+ * d_ws: device workspace of at least polar_batched_workspace_bytes(n_codes)
+ * bytes, reset by the call itself (no memset needed; the call can be captured
+ * into a HIP graph after one warm-up call has created the code tables).
+ * cfgs: per log2(N) launch configuration indexed by n - 6 (4 entries), or
+ * NULL.                                                                     */
+size_t polar_batched_workspace_bytes(int32_t n_codes);
+int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
+                            const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
+                            const int32_t *d_order, const pc_bp_params *bp,
+                            const pc_pp_params *pp, uint8_t *d_bits_pool,
+                            const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok,
+                            void *d_ws, size_t ws_bytes, const pc_launch_cfg *cfgs,
+                            void *stream);
+
+/* Weighted BP: the unrolled decoder with a learnable scale on every check-node
+ * output, w[t][s-1][d][row] (iteration t, stage s, d = 0 L sweep / 1 R sweep,
+ * output row), frozen prior 2^60, no early stop, T_unroll iterations; the
+ * output LLR is o_j = L_{n+1,j} + R_{n+1,j} after the last L sweep.  With
+ * pp != NULL and mode PC_PP_LASTK the fixed last-k schedule applies and the
+ * weights are shared by all trellises (indexed by stage position).
+ * d_w float [T_unroll][n][2][N]; d_out_llr float [F][N].  The forward pass
+ * writes per-iteration message checkpoints to d_ws, which must hold
+ * wbp_workspace_bytes(code, F, T_unroll) bytes and stay untouched until the
+ * matching wbp_backward.                                                    */
+size_t wbp_workspace_bytes(const pc_code *code, int64_t F, int32_t T_unroll);
+int wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                int32_t T_unroll, const pc_pp_params *pp, float *d_out_llr, void *d_ws,
+                size_t ws_bytes, void *stream);
+
+/* Reverse mode of wbp_forward: given d_grad_out float [F][N] (d loss / d o),
+ * writes d_grad_w float [T_unroll][n][2][N] = sum over frames of
+ * d loss / d w.  The reduction over frames has a fixed order, so results are
+ * reproducible run to run.  Same d_ws as the forward call.                  */
+int wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                 int32_t T_unroll, const pc_pp_params *pp, const float *d_grad_out,
+                 float *d_grad_w, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Static description of a return code, and the thread-local detail of the
+ * last failure on this thread.                                              */
+const char *polar_strerror(int rc);
+const char *polar_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLARBP_H */

@@ -1,0 +1,73 @@
+"""Build the HIP library ``libpolarbp.so`` for gfx950 with hipcc.
+
+Every translation unit is compiled in parallel into ``_build/`` and linked
+in-tree, so the library travels with the source tree.  The decode kernels are
+instantiated once per block length (PBP_NLOG = 1..12) in separate objects.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libpolarbp.so")
+
+HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("PBP_ARCH", "gfx950")
+
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    # IEEE arithmetic exactly as written: no fused multiply-add, no denormal flush
+    "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
+    # packed FP32 instructions are kept out of generated code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-lambda-capture",
+]
+
+
+def _units():
+    units = []
+    for n in range(1, 13):
+        units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
+    for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip"):
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        units.append((os.path.join(CSRC, src), os.path.splitext(src)[0] + ".o", lang))
+    return units
+
+
+def _compile(unit, extra):
+    src, obj, defs = unit
+    out = os.path.join(BUILD, obj)
+    cmd = [HIPCC, *FLAGS, *extra, *defs, "-c", src, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src} {defs}:\n{r.stdout}\n{r.stderr}")
+    return out
+
+
+def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    extra = extra or []
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    units = _units()
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(u, extra), units))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

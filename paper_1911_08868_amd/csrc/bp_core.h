@@ -1,0 +1,223 @@
+// bp_core.h -- device building blocks of the belief-propagation kernels
+// (gfx950, wave64): the stage-group plan, the thread -> row map, the
+// processing element of Sec. II-B and the register-resident group passes.
+//
+// Layout of one frame on the GPU.  A frame of N = 2^n rows is decoded by
+// TPS = N / 2^RHO threads; each thread owns 2^RHO rows of every level.  The n
+// stages are cut into groups of at most RHO consecutive stages; inside a
+// group all stage bits are register bits of the thread, so its processing
+// elements run on registers with no data exchange.  Only the two messages of
+// a group boundary level cross threads, through LDS, once per sweep.  The
+// persistent R messages and the L messages of the current iteration stay in
+// registers.
+//
+// Multi-trellis by relabelling.  BP on a graph whose stages 1..n use bits
+// e_1..e_n equals BP on the original graph after the rows are relabelled by
+// the bit permutation (relabelled bit s-1 = original bit e_s).  The permuted
+// last-k stages therefore run in relabelled coordinates with the same
+// register code as the original graph; only the accesses to the level below
+// the permuted range, the prior and the decisions go through the row map,
+// and the levels strictly inside the permuted range, which a permutation
+// resets anyway (Sec. III), never need moving.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+namespace pbp {
+
+template <int B, int E, class Fn>
+__device__ __forceinline__ void sfor(Fn &&fn) {
+    if constexpr (B < E) {
+        fn(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(fn);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time plan: n = log2 N, KP permuted last stages (0 = none), RHO =
+// log2 rows per thread per level.  Stages 1..n-KP (the unpermuted part) and
+// n-KP+1..n (the permuted part) are each split into groups of at most RHO
+// stages, so a group boundary sits at level n-KP (0-based level = number of
+// stages below it).
+template <int NLOG, int KP, int RHO>
+struct Plan {
+    static_assert(RHO >= 1 && RHO <= NLOG, "rows per thread exceed the frame");
+    static_assert(KP == 0 || (KP >= 2 && KP <= NLOG), "permuted range");
+    static constexpr int n = NLOG;
+    static constexpr int N = 1 << NLOG;
+    static constexpr int rho = RHO;
+    static constexpr int ROWS = 1 << RHO;
+    static constexpr int TPS = N / ROWS;
+    static constexpr int NB = NLOG - KP;
+    static constexpr int GB = (NB + RHO - 1) / RHO;
+    static constexpr int GT = (KP + RHO - 1) / RHO;
+    static constexpr int G = GB + GT;
+    static constexpr int kp = KP;
+    // first stage (0-based) of group g == its bottom level
+    static constexpr int lo(int g) {
+        if (g <= GB) {
+            int s = 0;
+            for (int i = 0; i < g; ++i) s += NB / GB + (i < NB % GB ? 1 : 0);
+            return s;
+        }
+        int s = NB;
+        for (int i = 0; i < g - GB; ++i) s += KP / GT + (i < KP % GT ? 1 : 0);
+        return s;
+    }
+    static constexpr int size(int g) { return lo(g + 1) - lo(g); }
+    static constexpr int RMAX = RHO;
+    static constexpr int RI = RHO > 1 ? RHO - 1 : 1;  // interior-level array extent
+    static constexpr int WPS = TPS >= 64 ? TPS / 64 : 1;  // waves per slot
+};
+
+// Thread -> row map of group g.  Register index i: its low r bits are the
+// group's stage bits (positions lo..lo+r-1); the thread index t fills the
+// remaining positions from the lowest up, and the high RHO-r bits of i fill
+// what is left.  Consecutive threads therefore touch consecutive rows
+// whenever lo > 0, and each thread's rows are contiguous when lo == 0.
+template <class P, int g>
+struct GMap {
+    static constexpr int lo = P::lo(g);
+    static constexpr int r = P::size(g);
+    static constexpr int tbits = P::n - P::rho;
+    static constexpr int off(int i) {
+        int low = i & ((1 << r) - 1), high = i >> r;
+        int o = low << lo;
+        int c = 0, hb = 0;
+        for (int p = 0; p < P::n; ++p) {
+            if (p >= lo && p < lo + r) continue;
+            if (c >= tbits) {
+                if ((high >> hb) & 1) o |= 1 << p;
+                ++hb;
+            }
+            ++c;
+        }
+        return o;
+    }
+    __device__ static __forceinline__ int base(int t) {
+        if constexpr (tbits <= lo) {
+            return t;
+        } else {
+            return (t & ((1 << lo) - 1)) | ((t >> lo) << (lo + r));
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Check function of the processing element (Sec. II-B): min-sum
+// sign(x) sign(y) min(|x|,|y|), optionally scaled.  The sign is the xor of the
+// sign bits; the magnitude min(|x|,|y|) is exact; the only rounding is that
+// of the scale.  Finite inputs and +inf priors never produce NaN.
+template <bool SCALED>
+__device__ __forceinline__ float cnode(float x, float y, float alpha) {
+    float m = __builtin_fminf(__builtin_fabsf(x), __builtin_fabsf(y));
+    if constexpr (SCALED) m = alpha * m;
+    uint32_t s = (__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u;
+    return __uint_as_float(__float_as_uint(m) | s);
+}
+
+// ---------------------------------------------------------------------------
+// Register state of one thread for one frame.
+template <class P>
+struct Regs {
+    float Rint[P::G][P::RI][P::ROWS];  // R on interior levels of each group (persistent)
+    float Lint[P::G][P::RI][P::ROWS];  // L on interior levels (current iteration)
+    float Lbot[P::G][P::ROWS];         // L on each group's bottom level
+    float Rtop[P::G][P::ROWS];         // R on each group's top level (g < G-1)
+    float Ltop[P::ROWS];               // L on level n after the last L sweep
+};
+
+// L sweep over the stages of group g: input L on its bottom level (Lbot),
+// R on its interior levels and top level; output L on its interior levels
+// and on its top level (returned in `out`).  `rtop` is the R of the top
+// level (the prior for the last group).
+template <class P, int g, bool SCALED>
+__device__ __forceinline__ void group_L(Regs<P> &S, const float (&rtop)[P::ROWS],
+                                        float (&out)[P::ROWS], float alpha) {
+    constexpr int r = P::size(g);
+    float cur[P::ROWS];
+    sfor<0, P::ROWS>([&](auto i) { cur[i] = S.Lbot[g][i]; });
+    sfor<0, r>([&](auto sl) {
+        float nxt[P::ROWS];
+        sfor<0, P::ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float r1, r2;
+                if constexpr (sl + 1 < r) {
+                    r1 = S.Rint[g][sl][i];
+                    r2 = S.Rint[g][sl][ip];
+                } else {
+                    r1 = rtop[i];
+                    r2 = rtop[ip];
+                }
+                const float l1 = cur[i], l2 = cur[ip];
+                nxt[i] = cnode<SCALED>(l1, l2 + r2, alpha);
+                nxt[ip] = cnode<SCALED>(r1, l1, alpha) + l2;
+            }
+        });
+        if constexpr (sl + 1 < r) {
+            sfor<0, P::ROWS>([&](auto i) { S.Lint[g][sl][i] = nxt[i]; });
+        }
+        sfor<0, P::ROWS>([&](auto i) { cur[i] = nxt[i]; });
+    });
+    sfor<0, P::ROWS>([&](auto i) { out[i] = cur[i]; });
+}
+
+// R sweep over the stages of group g, top to bottom: input R on its top level
+// (`rtop`), L on its interior and bottom levels; output R on its interior
+// levels and on its bottom level (returned in `out`).
+template <class P, int g, bool SCALED>
+__device__ __forceinline__ void group_R(Regs<P> &S, const float (&rtop)[P::ROWS],
+                                        float (&out)[P::ROWS], float alpha) {
+    constexpr int r = P::size(g);
+    float cur[P::ROWS];
+    sfor<0, P::ROWS>([&](auto i) { cur[i] = rtop[i]; });
+    sfor<0, r>([&](auto k) {
+        constexpr int sl = r - 1 - k;
+        float nxt[P::ROWS];
+        sfor<0, P::ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float l1, l2;
+                if constexpr (sl > 0) {
+                    l1 = S.Lint[g][sl - 1][i];
+                    l2 = S.Lint[g][sl - 1][ip];
+                } else {
+                    l1 = S.Lbot[g][i];
+                    l2 = S.Lbot[g][ip];
+                }
+                const float r1 = cur[i], r2 = cur[ip];
+                nxt[i] = cnode<SCALED>(r1, l2 + r2, alpha);
+                nxt[ip] = cnode<SCALED>(r1, l1, alpha) + r2;
+            }
+        });
+        if constexpr (sl > 0) {
+            sfor<0, P::ROWS>([&](auto i) { S.Rint[g][sl - 1][i] = nxt[i]; });
+        }
+        sfor<0, P::ROWS>([&](auto i) { cur[i] = nxt[i]; });
+    });
+    sfor<0, P::ROWS>([&](auto i) { out[i] = cur[i]; });
+}
+
+// relabelled row p -> original row for stage order e[0..n-1]: bit s of p is
+// bit e[s] of the original row.  Only bits lowbits..n-1 can move.
+__device__ __forceinline__ int relabel_to_row(int p, const int8_t *e, int n, int lowbits) {
+    int j = p & ((1 << lowbits) - 1);
+    for (int s = lowbits; s < n; ++s) j |= ((p >> s) & 1) << e[s];
+    return j;
+}
+
+// xor-reduce over groups of `width` consecutive lanes (width a power of two
+// <= 64); every lane of the group receives the result
+__device__ __forceinline__ uint32_t xor_reduce(uint32_t v, int width) {
+    for (int m = 1; m < width; m <<= 1) v ^= (uint32_t)__shfl_xor((int)v, m, 64);
+    return v;
+}
+
+}  // namespace pbp

@@ -1,0 +1,349 @@
+// decode_kernel.h -- persistent PP-MT-BP decoding kernel (gfx950).
+//
+// One workgroup holds `S` frame slots of TPS threads each.  All slots run the
+// same sequence of group passes in lock step (workgroup barriers between
+// passes); each slot is at its own iteration of its own frame.  A slot whose
+// frame stops (CRC or G test, Sec. IV) or reaches N_it,max writes its outputs
+// and takes the next frame from a device queue (one atomic per frame), so
+// frames that stop early never leave their lanes idle while a long frame
+// finishes.  The workgroup exits when the queue is empty and every slot is
+// done.
+//
+// Per iteration (Algorithm 1, oneBPiteration): L passes of groups 0..G-2
+// (channel side to u side), the last group's L pass, hard decision and CRC
+// syndrome, the last group's R pass, then R passes of groups G-2..0.  A CRC
+// stop is decided right after the decision, which does not depend on the R
+// sweep, so a stopping frame skips the rest of the sweep.  Between
+// iterations a frame that has not stopped switches trellis at multiples of T.
+#pragma once
+
+#include "bp_core.h"
+
+namespace pbp {
+
+struct DecodeArgs {
+    const float *llr;
+    int64_t F;
+    uint8_t *msg;
+    int32_t *iters;
+    uint8_t *ok;
+    float *soft;
+    const uint32_t *syn;
+    const int32_t *meta;
+    uint32_t *counter;
+    int32_t K_msg, max_iter, it_min, stop;
+    float alpha;
+    int32_t T, Q;
+    int8_t orders[8][16];
+};
+
+template <class P>
+struct DecodeLds {
+    static constexpr int NW = (P::N + 31) / 32;
+    // bytes of dynamic LDS for S slots
+    static constexpr size_t bytes(int S) {
+        return (size_t)S * 4 * P::N * sizeof(float)   // L/R boundary ping-pong buffers
+               + (size_t)S * sizeof(int)                // frame of each slot
+               + (size_t)S * P::WPS * sizeof(uint32_t)  // syndrome partials
+               + (size_t)S * 2 * NW * sizeof(uint32_t)  // G test words (u_hat, x_hat)
+               + (size_t)S * sizeof(int)                // G test verdict
+               + 8 * 16;                                // stage orders of the pool
+    }
+};
+
+// launch bound: one frame's threads, at least 256
+template <int NLOG, int RHO>
+constexpr int decode_launch_bound() {
+    return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
+}
+
+template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE>
+__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()))
+k_decode(DecodeArgs a) {
+    using P = Plan<NLOG, KP, RHO>;
+    constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG;
+    constexpr int GB = P::GB;
+    constexpr int NW = DecodeLds<P>::NW;
+    constexpr int WPS = P::WPS;
+    constexpr bool MAPPED_BOUNDARY = (KP > 0 && KP < NLOG);
+    constexpr int LOWBITS = NLOG - KP;
+
+    const int tid = threadIdx.x;
+    const int S = blockDim.x / TPS;
+    const int slot = tid / TPS;
+    const int t = tid & (TPS - 1);
+
+    extern __shared__ __align__(16) float smem[];
+    float *const buf = smem + (size_t)slot * 4 * N;  // [L0 | L1 | R0 | R1]
+    int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * N);
+    uint32_t *const synpart = reinterpret_cast<uint32_t *>(frame_slot + S);
+    uint32_t *const gwords = synpart + S * WPS;
+    int *const gflag = reinterpret_cast<int *>(gwords + S * 2 * NW);
+    int8_t *const ords = reinterpret_cast<int8_t *>(gflag + S);
+
+    if (tid < 8 * 16) ords[tid] = a.orders[tid >> 4][tid & 15];
+    if constexpr (GMODE) {
+        for (int w = tid; w < S * 2 * NW; w += blockDim.x) gwords[w] = 0u;
+    }
+
+    Regs<P> st;
+    uint32_t synv[ROWS];
+    int metav[ROWS];
+    int baddr[ROWS];
+    uint32_t frozen_bits = 0, ubits = 0;
+    int it = 0, q = 0, frame = 0;
+    bool active = false, need_new = true;
+    const float alpha = a.alpha;
+    const float inf = __builtin_huge_valf();
+
+    // --- per-frame (re)initialisation helpers ------------------------------
+    auto load_top_info = [&](int qq) {
+        const int8_t *e = ords + qq * 16;
+        frozen_bits = 0;
+        const int base = GMap<P, G - 1>::base(t);
+        sfor<0, ROWS>([&](auto i) {
+            int p = base + GMap<P, G - 1>::off(i);
+            int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+            int m = a.meta[j];
+            metav[i] = m;
+            synv[i] = a.syn[j];
+            frozen_bits |= (m == -2 ? 1u : 0u) << i;
+        });
+        if constexpr (MAPPED_BOUNDARY) {
+            const int bb = GMap<P, GB>::base(t);
+            sfor<0, ROWS>([&](auto i) {
+                baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS);
+            });
+        }
+    };
+    auto load_channel = [&](int qq) {
+        const float *src = a.llr + (int64_t)frame * N;
+        const int base = GMap<P, 0>::base(t);
+        if constexpr (KP == NLOG) {
+            const int8_t *e = ords + qq * 16;
+            sfor<0, ROWS>([&](auto i) {
+                st.Lbot[0][i] = src[relabel_to_row(base + GMap<P, 0>::off(i), e, n, 0)];
+            });
+        } else {
+            sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[base + GMap<P, 0>::off(i)]; });
+        }
+    };
+    auto start_frame = [&]() {
+        it = 0;
+        q = 0;
+        sfor<0, G>([&](auto g) {
+            sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
+            sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
+        });
+        load_channel(0);
+        load_top_info(0);
+    };
+    // trellis switch (Sec. III): levels strictly inside the permuted range are
+    // reset; in relabelled coordinates nothing else moves
+    auto apply_event = [&]() {
+        sfor<GB, G>([&](auto g) {
+            sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
+            if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
+        });
+        if constexpr (KP == NLOG) load_channel(q);
+        load_top_info(q);
+    };
+
+    for (;;) {
+        // ---- queue: refill finished slots --------------------------------
+        if (need_new && t == 0) frame_slot[slot] = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        if (need_new) {
+            frame = frame_slot[slot];
+            active = frame < a.F;
+            need_new = false;
+            if (active) start_frame();
+        }
+        {
+            bool any = false;
+            for (int s = 0; s < S; ++s) any |= frame_slot[s] < a.F;
+            if (!any) break;
+        }
+
+        // ---- L sweep: groups 0..G-2 ---------------------------------------
+        sfor<0, G - 1>([&](auto g) {
+            if (active) {
+                if constexpr (g > 0) {
+                    const float *lb = buf + (g & 1) * N;
+                    if constexpr (MAPPED_BOUNDARY && g == GB) {
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
+                    } else {
+                        const int base = GMap<P, g>::base(t);
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+                    }
+                }
+                float out[ROWS];
+                group_L<P, g, SCALED>(st, st.Rtop[g], out, alpha);
+                float *lt = buf + ((g + 1) & 1) * N;
+                const int base = GMap<P, g>::base(t);
+                sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+            }
+            __syncthreads();
+        });
+
+        // ---- last group: L pass, decision, R pass ---------------------------
+        if (active) {
+            if constexpr (G > 1) {
+                const float *lb = buf + ((G - 1) & 1) * N;
+                if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+                } else {
+                    const int base = GMap<P, G - 1>::base(t);
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
+                }
+            }
+            float prior[ROWS];
+            sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? inf : 0.f; });
+            group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
+            // hard decision (Sec. II-B): 1 iff L + R < 0; frozen rows stay 0
+            uint32_t syn = 0;
+            ubits = 0;
+            sfor<0, ROWS>([&](auto i) {
+                const bool u = !((frozen_bits >> i) & 1u) && (st.Ltop[i] < 0.f);
+                ubits |= (u ? 1u : 0u) << i;
+                syn ^= u ? synv[i] : 0u;
+            });
+            float rb[ROWS];
+            group_R<P, G - 1, SCALED>(st, prior, rb, alpha);
+            if constexpr (G > 1) {
+                float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
+                    sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                } else {
+                    const int base = GMap<P, G - 1>::base(t);
+                    sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
+                }
+            }
+            if constexpr (!GMODE) {
+                syn = xor_reduce(syn, TPS < 64 ? TPS : 64);
+                if ((t & 63) == 0) synpart[slot * WPS + (t >> 6)] = syn;
+            } else {
+                uint32_t *U = gwords + slot * 2 * NW;
+                const int base = GMap<P, G - 1>::base(t);
+                sfor<0, ROWS>([&](auto i) {
+                    if ((ubits >> i) & 1u) {
+                        const int j = base + GMap<P, G - 1>::off(i);
+                        atomicOr(&U[j >> 5], 1u << (j & 31));
+                    }
+                });
+                if constexpr (G == 1) {
+                    uint32_t *X = U + NW;
+                    sfor<0, ROWS>([&](auto i) {
+                        if (st.Lbot[0][i] + rb[i] < 0.f) {
+                            const int j = base + GMap<P, 0>::off(i);
+                            atomicOr(&X[j >> 5], 1u << (j & 31));
+                        }
+                    });
+                }
+            }
+        }
+        __syncthreads();
+
+        bool finishing = false, pass = false;
+        if constexpr (!GMODE) {
+            if (active) {
+                uint32_t s = 0;
+                for (int w = 0; w < WPS; ++w) s ^= synpart[slot * WPS + w];
+                pass = (s == 0u);
+                finishing = (it + 1 == a.max_iter) || (a.stop == 2 && it + 1 >= a.it_min && pass);
+            }
+        }
+
+        // ---- R sweep: groups G-2..0 ----------------------------------------
+        sfor<0, G - 1>([&](auto k) {
+            constexpr int g = G - 2 - k;
+            if (active && !finishing) {
+                const float *rsrc = buf + 2 * N + ((g + 1) & 1) * N;
+                const int base = GMap<P, g>::base(t);
+                sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rsrc[base + GMap<P, g>::off(i)]; });
+                float rb[ROWS];
+                group_R<P, g, SCALED>(st, st.Rtop[g], rb, alpha);
+                if constexpr (g > 0) {
+                    float *rt = buf + 2 * N + (g & 1) * N;
+                    if constexpr (MAPPED_BOUNDARY && g == GB) {
+                        sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                    } else {
+                        sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                    }
+                } else if constexpr (GMODE) {
+                    uint32_t *X = gwords + slot * 2 * NW + NW;
+                    sfor<0, ROWS>([&](auto i) {
+                        if (st.Lbot[0][i] + rb[i] < 0.f) {
+                            const int j = base + GMap<P, 0>::off(i);
+                            atomicOr(&X[j >> 5], 1u << (j & 31));
+                        }
+                    });
+                }
+            }
+            __syncthreads();
+        });
+
+        if constexpr (GMODE) {
+            // G test (stopping criterion of the G-matrix kind): u_hat G_N == x_hat
+            if (active && t == 0) {
+                uint32_t *U = gwords + slot * 2 * NW, *X = U + NW;
+                uint32_t w[NW];
+                for (int i = 0; i < NW; ++i) w[i] = U[i];
+                constexpr uint32_t M[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
+                                           0x0000FFFFu};
+                for (int b = 0; b < n && b < 5; ++b)
+                    for (int i = 0; i < NW; ++i) w[i] ^= (w[i] >> (1 << b)) & M[b];
+                for (int b = 5; b < n; ++b)
+                    for (int i = 0; i < NW; ++i)
+                        if (!((i >> (b - 5)) & 1)) w[i] ^= w[i | (1 << (b - 5))];
+                uint32_t diff = 0;
+                const uint32_t last = (N >= 32) ? 0xFFFFFFFFu : ((1u << N) - 1u);
+                for (int i = 0; i < NW; ++i) diff |= (w[i] ^ X[i]) & (i == NW - 1 ? last : 0xFFFFFFFFu);
+                gflag[slot] = diff == 0u;
+                for (int i = 0; i < 2 * NW; ++i) U[i] = 0u;
+            }
+            __syncthreads();
+            if (active) {
+                pass = gflag[slot] != 0;
+                finishing = (it + 1 == a.max_iter) || (a.stop == 1 && it + 1 >= a.it_min && pass);
+            }
+        }
+
+        // ---- bookkeeping -----------------------------------------------------
+        if (active) {
+            if (finishing) {
+                const int64_t mo = (int64_t)frame * a.K_msg;
+                sfor<0, ROWS>([&](auto i) {
+                    if (metav[i] >= 0) a.msg[mo + metav[i]] = (uint8_t)((ubits >> i) & 1u);
+                });
+                if (a.soft) {
+                    const int8_t *e = ords + q * 16;
+                    const int base = GMap<P, G - 1>::base(t);
+                    sfor<0, ROWS>([&](auto i) {
+                        const int p = base + GMap<P, G - 1>::off(i);
+                        const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+                        a.soft[(int64_t)frame * N + j] = st.Ltop[i];
+                    });
+                }
+                if (t == 0) {
+                    if (a.iters) a.iters[frame] = it + 1;
+                    if (a.ok) a.ok[frame] = pass ? 1 : 0;
+                }
+                need_new = true;
+            } else {
+                it += 1;
+                if constexpr (KP > 0) {
+                    if (a.Q > 1 && (it % a.T) == 0) {
+                        const int qn = (it / a.T) % a.Q;
+                        if (qn != q) {
+                            q = qn;
+                            apply_event();
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace pbp

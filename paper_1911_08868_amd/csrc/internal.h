@@ -1,0 +1,91 @@
+// internal.h -- shared declarations of the polarbp library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/polarbp.h"
+
+namespace pbp {
+
+constexpr int kMaxN = 4096;
+constexpr int kMaxLog = 12;
+constexpr int kMaxPool = 8;
+
+// Device-side per-row tables of one code.  meta[j]: >= 0 message index of
+// row j, -1 CRC position, -2 frozen.  syn[j]: CRC syndrome contribution of a
+// decided 1 at row j (0 for frozen rows); the syndrome of a decision vector
+// is the xor of syn over its ones and is 0 exactly when the CRC matches.
+struct DeviceTables {
+    uint32_t *syn = nullptr;
+    int32_t *meta = nullptr;
+    int32_t *info = nullptr;   // K information rows, ascending
+    uint32_t *crc_of_msg_bit = nullptr;  // [K_msg] CRC of the unit message e_i
+};
+
+}  // namespace pbp
+
+struct pc_code {
+    int32_t N = 0, n = 0, K = 0, crc_width = 0, K_msg = 0;
+    uint32_t crc_poly = 0;
+    int device = 0;
+    std::vector<int32_t> info;
+    std::vector<uint8_t> frozen;
+    std::vector<uint32_t> syn;
+    std::vector<int32_t> meta;
+    std::vector<uint32_t> crc_of_msg_bit;
+    pbp::DeviceTables d;
+};
+
+namespace pbp {
+
+void set_error(const std::string &msg);
+int fail(int rc, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+// trellis pool (SplitMix64 + Fisher-Yates); returns number of entries
+int make_pool(int n, int k, int Q, uint64_t seed, int8_t *orders);
+
+// number of compute units of the current device (cached)
+int device_cu_count();
+
+// per-call queue counter in a library-owned device ring
+uint32_t *next_counter(int device);
+
+// ---- decode ----------------------------------------------------------------
+struct DecodeConfig {
+    int n = 0, kp = 0;         // log2 N, permuted stages (0 = none)
+    bool scaled = false;       // alpha != 1
+    bool gmode = false;        // G-matrix test machinery
+    int rho = 2, slots = 1, grid = 0;
+};
+
+int launch_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params &bp,
+                  int pp_mode, int kp, int T, int Q, const int8_t *orders, uint8_t *d_msg,
+                  int32_t *d_iters, uint8_t *d_ok, float *d_soft, const pc_launch_cfg *cfg,
+                  hipStream_t stream);
+
+int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
+                  hipStream_t stream);
+
+int launch_batched(const pc_code *const *codes, int n_codes, const int32_t *d_code_id,
+                   const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
+                   const int32_t *d_order, const pc_bp_params &bp, int kp_req, int T, int Q,
+                   uint64_t seed, uint8_t *d_bits, const int64_t *d_bits_off, int32_t *d_iters,
+                   uint8_t *d_ok, void *d_ws, size_t ws_bytes, const pc_launch_cfg *cfgs,
+                   hipStream_t stream);
+size_t batched_ws_bytes(int n_codes);
+
+size_t wbp_ws_bytes(const pc_code *code, int64_t F, int T);
+int launch_wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                       int T, int kp, int Tev, int Q, const int8_t *orders, float *d_out,
+                       void *d_ws, size_t ws_bytes, hipStream_t stream);
+int launch_wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                        int T, int kp, int Tev, int Q, const int8_t *orders,
+                        const float *d_gout, float *d_gw, void *d_ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+}  // namespace pbp

@@ -1,0 +1,242 @@
+"""GPU parity of construction, encoding and decoding against the CPU oracle.
+
+Every comparison is element by element on the same seeded inputs: message
+bits, iteration counts and verdicts bit-exact, and the u-side L messages
+(FP32) bit-exact against the oracle's FP32 mode, which performs the same
+operations in the same order.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pbp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1911_08868_amd as m
+    return m
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def frames(orc, N, K, cw, poly, F, snr, seed, dsnr=2.5, all_zero=False):
+    oc = orc.construct(N, K, dsnr, cw, poly)
+    msg = synth.message_bits(seed, F, oc.K_msg, all_zero=all_zero)
+    _, x = orc.encode(oc, msg)
+    llr = synth.awgn_llr(x, snr, oc.K_msg, seed=seed)
+    return oc, msg, llr
+
+
+def gpu_code(pbp, oc, dsnr=2.5):
+    c = pbp.Code(oc.N, oc.K, oc.crc_width, oc.crc_poly, dsnr)
+    assert np.array_equal(c.info_idx, oc.info_idx)
+    assert np.array_equal(c.frozen, oc.frozen)
+    return c
+
+
+def run_both(orc, pbp, oc, llr, max_iter, stop, it_min=1, alpha=1.0, pp_mode=-1, k=0, T=1, Q=1,
+             seed=0, cfg=None, dsnr=2.5):
+    torch = _torch()
+    code = gpu_code(pbp, oc, dsnr)
+    bp = pbp.BPParams(max_iter=max_iter, alpha=alpha, stop=stop, it_min=it_min)
+    pp = pbp.PPParams(mode=pp_mode, k=k, period_T=T, pool_Q=Q, seed=seed)
+    d = torch.from_numpy(llr).cuda()
+    msg, iters, ok, soft = pbp.pp_mt_bp_decode(code, d, bp, pp, soft=True, cfg=cfg)
+    torch.cuda.synchronize()
+    ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=max_iter, alpha=alpha, stop=stop,
+                                               it_min=it_min, pp_mode=pp_mode, k=k, T=T, Q=Q,
+                                               seed=seed, fp32=True), soft=True, threads=8)
+    return (msg.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy(), soft.cpu().numpy()), ref
+
+
+def assert_parity(got, ref, tag=""):
+    msg, iters, ok, soft = got
+    F = msg.shape[0]
+    bad = np.nonzero((msg != ref.msg_hat).any(1) | (iters != ref.iters) | (ok != ref.ok))[0]
+    assert bad.size == 0, f"{tag}: {bad.size}/{F} frames differ, first {bad[:5]}, " \
+                          f"iters {iters[bad[:5]]} vs {ref.iters[bad[:5]]}"
+    want = ref.soft_u.astype(np.float32)
+    assert np.array_equal(soft.view(np.uint32), want.view(np.uint32)), f"{tag}: soft messages differ"
+
+
+def test_construction_matches_oracle(orc, pbp):
+    for N, K, cw, poly, dsnr in [(64, 32, 0, 0, 2.0), (1024, 512, 16, 0x1021, 2.5),
+                                 (4096, 2072, 24, 0x1864CFB, 2.5), (256, 144, 16, 0x1021, 2.5),
+                                 (2, 1, 0, 0, 0.0), (128, 43, 16, 0x1021, 2.5)]:
+        gpu_code(pbp, orc.construct(N, K, dsnr, cw, poly), dsnr)
+
+
+@pytest.mark.parametrize("N,K,cw,poly", [(64, 32, 0, 0), (1024, 512, 16, 0x1021),
+                                         (4096, 2072, 24, 0x1864CFB), (8, 5, 3, 0x3),
+                                         (2, 2, 0, 0), (512, 100, 16, 0x1021)])
+def test_encoder_bit_exact(orc, pbp, N, K, cw, poly):
+    torch = _torch()
+    oc = orc.construct(N, K, 2.5, cw, poly)
+    code = gpu_code(pbp, oc)
+    for F in (1, 37, 1000):
+        msg = synth.message_bits(N + F, F, oc.K_msg)
+        _, x = orc.encode(oc, msg)
+        got = pbp.encode(code, torch.from_numpy(msg).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), x)
+
+
+@pytest.mark.parametrize("snr", [1.0, 2.0, 3.0, 4.0])
+@pytest.mark.parametrize("all_zero", [True, False])
+def test_plain_bp_n64_gtest_scaled(orc, pbp, snr, all_zero):
+    # N = 64, K = 32, no CRC, scaled min-sum 0.9375, G-matrix stop, 40 iterations
+    oc, msg, llr = frames(orc, 64, 32, 0, 0, 500, snr, seed=int(snr * 10) + all_zero,
+                          dsnr=2.0, all_zero=all_zero)
+    got, ref = run_both(orc, pbp, oc, llr, 40, orc.STOP_G, alpha=0.9375, dsnr=2.0)
+    assert_parity(got, ref, f"N64 snr={snr}")
+
+
+@pytest.mark.parametrize("mode,k,T", [(-1, 0, 1), (0, 3, 5), (0, 4, 10), (0, 5, 5), (0, 5, 10),
+                                      (1, 10, 25), (0, 2, 3)])
+def test_n1024_parity(orc, pbp, mode, k, T):
+    oc, msg, llr = frames(orc, 1024, 512, 16, 0x1021, 160, 2.0, seed=7 + k + T)
+    got, ref = run_both(orc, pbp, oc, llr, 200, orc.STOP_CRC, it_min=3, pp_mode=mode, k=k, T=T,
+                        Q=8, seed=11)
+    assert_parity(got, ref, f"mode={mode} k={k} T={T}")
+
+
+@pytest.mark.parametrize("rho,slots,grid", [(2, 1, 0), (3, 1, 0), (3, 2, 0), (3, 2, 3),
+                                            (2, 1, 1), (2, 1, 7)])
+def test_launch_shapes_and_refill(orc, pbp, rho, slots, grid):
+    # few workgroups force many queue refills per slot
+    oc, msg, llr = frames(orc, 1024, 512, 16, 0x1021, 61, 1.75, seed=3)
+    got, ref = run_both(orc, pbp, oc, llr, 120, orc.STOP_CRC, it_min=3, pp_mode=0, k=4, T=10,
+                        Q=8, seed=2, cfg=pbp.LaunchCfg(rho, slots, grid))
+    assert_parity(got, ref, f"rho={rho} slots={slots} grid={grid}")
+
+
+@pytest.mark.parametrize("N,K,k", [(128, 43, 4), (256, 128, 4), (512, 384, 4), (128, 96, 4),
+                                   (256, 64, 3)])
+def test_mixed_lengths_parity(orc, pbp, N, K, k):
+    oc, msg, llr = frames(orc, N, K, 16, 0x1021, 200, 2.5, seed=N + K)
+    got, ref = run_both(orc, pbp, oc, llr, 200, orc.STOP_CRC, it_min=3, pp_mode=0, k=k, T=10,
+                        Q=8, seed=5)
+    assert_parity(got, ref, f"N={N} K={K}")
+
+
+def test_n4096_crc24_parity(orc, pbp):
+    oc, msg, llr = frames(orc, 4096, 2072, 24, 0x1864CFB, 12, 2.0, seed=40)
+    for rho in (2, 3):
+        got, ref = run_both(orc, pbp, oc, llr, 60, orc.STOP_CRC, it_min=3, pp_mode=0, k=5, T=10,
+                            Q=8, seed=6, cfg=pbp.LaunchCfg(rho, 0, 0))
+        assert_parity(got, ref, f"N4096 rho={rho}")
+
+
+@pytest.mark.parametrize("N,K", [(2, 1), (2, 2), (4, 2), (8, 4), (16, 8), (32, 17)])
+def test_tiny_codes(orc, pbp, N, K):
+    oc, msg, llr = frames(orc, N, K, 0, 0, 300, 2.0, seed=N * 7 + K, dsnr=1.0)
+    got, ref = run_both(orc, pbp, oc, llr, 12, orc.STOP_G, dsnr=1.0)
+    assert_parity(got, ref, f"N={N}")
+    got, ref = run_both(orc, pbp, oc, llr, 5, orc.STOP_NONE, alpha=0.75, dsnr=1.0)
+    assert_parity(got, ref, f"N={N} none")
+
+
+def test_edge_cases(orc, pbp):
+    torch = _torch()
+    oc, msg, llr = frames(orc, 256, 144, 16, 0x1021, 9, 1.5, seed=1)
+    # max_iter = 1, it_min larger than max_iter, stop none with CRC verdict
+    for mi, im, stop in [(1, 1, orc.STOP_CRC), (5, 9, orc.STOP_CRC), (7, 1, orc.STOP_NONE)]:
+        got, ref = run_both(orc, pbp, oc, llr, mi, stop, it_min=im, pp_mode=0, k=3, T=2, Q=4,
+                            seed=1)
+        assert_parity(got, ref, f"max_iter={mi} it_min={im}")
+    # K = N: no frozen rows
+    oc2, msg2, llr2 = frames(orc, 64, 64, 16, 0x1021, 50, 6.0, seed=2)
+    got, ref = run_both(orc, pbp, oc2, llr2, 10, orc.STOP_CRC)
+    assert_parity(got, ref, "K=N")
+    # F = 0 is a no-op
+    code = gpu_code(pbp, oc)
+    empty = torch.empty((0, 256), dtype=torch.float32, device="cuda")
+    pbp.pp_mt_bp_decode(code, empty, pbp.BPParams(), pbp.PPParams())
+    # noiseless codewords decode in one iteration
+    oc3 = orc.construct(1024, 512, 2.5, 16, 0x1021)
+    m3 = synth.message_bits(5, 40, oc3.K_msg)
+    _, x3 = orc.encode(oc3, m3)
+    l3 = synth.awgn_llr(x3, 3.0, oc3.K_msg, seed=0, noiseless=True)
+    c3 = gpu_code(pbp, oc3)
+    msg, iters, ok = pbp.bp_decode(c3, torch.from_numpy(l3).cuda(),
+                                   pbp.BPParams(max_iter=10, stop=pbp.STOP_CRC))
+    assert np.array_equal(msg.cpu().numpy(), m3)
+    assert np.all(iters.cpu().numpy() == 1) and np.all(ok.cpu().numpy() == 1)
+
+
+def test_invalid_arguments(pbp):
+    torch = _torch()
+    with pytest.raises(pbp.PolarError):
+        pbp.Code(1000, 500)
+    with pytest.raises(pbp.PolarError):
+        pbp.Code(64, 10, 16, 0x1021)      # crc_width >= K
+    code = pbp.Code(64, 32)
+    llr = torch.zeros((4, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(pbp.PolarError):   # CRC stop without CRC
+        pbp.bp_decode(code, llr, pbp.BPParams(stop=pbp.STOP_CRC))
+    with pytest.raises(pbp.PolarError):
+        pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(stop=pbp.STOP_NONE),
+                            pbp.PPParams(mode=pbp.PP_LASTK, k=7))
+    with pytest.raises(pbp.PolarError):
+        pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(stop=pbp.STOP_NONE),
+                            pbp.PPParams(mode=pbp.PP_ALG1))
+    with pytest.raises(pbp.PolarError):
+        pbp.bp_decode(code, llr, pbp.BPParams(max_iter=0, stop=pbp.STOP_NONE))
+    big = pbp.Code(1024, 512, 16, 0x1021)
+    l2 = torch.zeros((4, 1024), dtype=torch.float32, device="cuda")
+    with pytest.raises(pbp.PolarError):   # 4 slots of 256 threads exceed the launch bound
+        pbp.pp_mt_bp_decode(big, l2, pbp.BPParams(), pbp.PPParams(), cfg=pbp.LaunchCfg(2, 4, 0))
+
+
+def test_full_size_n1024_sampled(orc, pbp):
+    """The bench workload's shape: 1e6 frames of N = 1024 in one launch with the
+    default launch shape; 256 sampled frames checked one by one against the
+    oracle, and the frame error rate against the oracle's FP64 interval."""
+    from scipy.stats import beta
+    torch = _torch()
+    oc = orc.construct(1024, 512, 2.5, 16, 0x1021)
+    code = gpu_code(pbp, oc)
+    F, pool = 1_000_000, 2048
+    msgs = synth.message_bits(77, pool, oc.K_msg)
+    _, xs = orc.encode(oc, msgs)
+    idx = torch.arange(F, device="cuda") % pool
+    x = torch.from_numpy(xs).cuda()[idx]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    llr = synth.awgn_llr_torch(x, 2.5, oc.K_msg, gen)
+    del x
+    bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
+    msg, iters, ok = pbp.pp_mt_bp_decode(code, llr, bp, pp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(F, 256, replace=False))
+    s_llr = llr[torch.from_numpy(sample).cuda()].cpu().numpy()
+    ref = orc.decode(oc, s_llr, orc.DecodeParams(max_iter=200, stop=orc.STOP_CRC, it_min=3,
+                                                 pp_mode=0, k=4, T=10, Q=8, seed=1), threads=8)
+    g_msg = msg[torch.from_numpy(sample).cuda()].cpu().numpy()
+    assert np.array_equal(g_msg, ref.msg_hat)
+    assert np.array_equal(iters.cpu().numpy()[sample], ref.iters)
+    assert np.array_equal(ok.cpu().numpy()[sample], ref.ok)
+    # frame errors over all frames against the FP64 oracle on 2000 fresh frames
+    want = torch.from_numpy(msgs).cuda()[idx]
+    fer_gpu = (msg != want).any(1).double().mean().item()
+    oc_l = synth.awgn_llr(np.repeat(xs[:1], 1, 0), 2.5, oc.K_msg, seed=1)  # warm path
+    m2 = synth.message_bits(91, 2000, oc.K_msg)
+    _, x2 = orc.encode(oc, m2)
+    l2 = synth.awgn_llr(x2, 2.5, oc.K_msg, seed=91)
+    r64 = orc.decode(oc, l2, orc.DecodeParams(max_iter=200, stop=orc.STOP_CRC, it_min=3,
+                                              pp_mode=0, k=4, T=10, Q=8, seed=1, fp32=False),
+                     threads=8)
+    e = int((r64.msg_hat != m2).any(1).sum())
+    lo = beta.ppf(0.025, e, 2000 - e + 1) if e else 0.0
+    hi = beta.ppf(0.975, e + 1, 2000 - e)
+    assert lo <= fer_gpu <= hi, (fer_gpu, lo, hi)
+    del oc_l
