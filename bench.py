@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of PP-MT-BP polar decoding on one MI355X.
+
+Workload (one step): N = 1024 polar code, K = 512 = 496 message bits + CRC-16
+(0x1021), Bhattacharyya frozen set at design Eb/N0 = 2.5 dB, BPSK-AWGN frames
+at Eb/N0 = 1.5, 1.75, ..., 3.5 dB (9 points) with --frames frames per point
+(default 1e6), decoded by partially permuted multi-trellis BP in FP32: the
+last k = 4 of the 10 stages re-ordered from a seeded pool of Q = 8 trellises
+every T = 10 iterations, at most 200 iterations, CRC early stop from
+iteration 3.  Inputs (channel LLRs) are generated in device memory before the
+timed region.  value = decoded message bits per second over the whole step.
+
+Prints one JSON line.  Extra fields: per-Eb/N0 breakdown, plain BP and full
+permutation on the same frames, weighted-BP training throughput and the
+mixed-length batched decode, a roofline entry for the decode kernel, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, K, CRC_W, CRC_POLY, DESIGN_DB = 1024, 512, 16, 0x1021, 2.5
+K_MSG = K - CRC_W
+SNRS = [1.5 + 0.25 * i for i in range(9)]
+MAX_ITER, IT_MIN = 200, 3
+PP_K, PP_T, PP_Q, PP_SEED = 4, 10, 8, 1
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one non-packed 32-bit VALU
+# operation per lane per clock (the 157.3 TFLOP/s fp32 figure counts packed FMA
+# as 4 flops per lane-clock)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 128 B/clk/CU
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip side variants")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("bp_core.h", "decode_kernel.h", "decode_inst.h"):
+        with open(os.path.join(ROOT, "paper_1911_08868_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_inputs(pbp, code, frames, torch, seed=2024):
+    """LLRs [len(SNRS)][frames, N] in device memory: random messages encoded on
+    the GPU, BPSK over AWGN (synth's channel model)."""
+    import synth
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    llrs, msgs = [], []
+    for si, snr in enumerate(SNRS):
+        m = torch.randint(0, 2, (frames, K_MSG), generator=gen, device="cuda", dtype=torch.uint8)
+        x = pbp.encode(code, m)
+        llrs.append(synth.awgn_llr_torch(x, snr, K_MSG, gen))
+        del x
+        msgs.append(m)
+    torch.cuda.synchronize()
+    return llrs, msgs
+
+
+def alg_ops(iters):
+    """Algorithmic VALU lane-ops of a decode launch: every processing element
+    (n N/2 per sweep) costs 2 min-sum evaluations (min of magnitudes, sign xor,
+    sign apply) and 2 additions, 8 ops, so a sweep costs 4 n N.  A frame needs
+    `iters` L sweeps and iters - 1 R sweeps (the R sweep after the deciding L
+    sweep cannot change the output)."""
+    n = 10
+    per_sweep = 4 * n * N
+    return per_sweep * (2.0 * iters.double().sum().item() - iters.numel())
+
+
+def run_decode_set(pbp, code, llrs, outs, bp, pp, torch, events=None):
+    for si in range(len(SNRS)):
+        if events is not None:
+            events[si][0].record()
+        pbp.pp_mt_bp_decode(code, llrs[si], bp, pp, out=outs[si])
+        if events is not None:
+            events[si][1].record()
+
+
+def cpu_baseline(args):
+    """The oracle, as is, on a bounded sample of the same workload generated on
+    the host; threads = the host share of cores it actually uses."""
+    import numpy as np
+    import oracle
+    import synth
+    threads = min(16, os.cpu_count() or 1)
+    oc = oracle.construct(N, K, DESIGN_DB, CRC_W, CRC_POLY)
+    p = oracle.DecodeParams(max_iter=MAX_ITER, stop=oracle.STOP_CRC, it_min=IT_MIN,
+                            pp_mode=oracle.PP_LASTK, k=PP_K, T=PP_T, Q=PP_Q, seed=PP_SEED,
+                            fp32=True)
+    per = 16 * threads  # frames per Eb/N0 point in the first round; grown to fill the budget
+    total_frames, total_time = 0, 0.0
+    rounds = 0
+    while total_time < args.cpu_seconds and rounds < 6:
+        for si, snr in enumerate(SNRS):
+            msg = synth.message_bits(1000 + rounds * 31 + si, per, K_MSG)
+            _, x = oracle.encode(oc, msg)
+            llr = synth.awgn_llr(x, snr, K_MSG, seed=2000 + rounds * 31 + si)
+            t0 = time.perf_counter()
+            oracle.decode(oc, llr, p, threads=threads)
+            total_time += time.perf_counter() - t0
+            total_frames += per
+        rounds += 1
+        if total_time < args.cpu_seconds / 4:
+            per *= 4
+    gbps = total_frames * K_MSG / total_time / 1e9
+    return {"value": gbps, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
+            "sample": f"{total_frames} frames spread evenly over the 9 Eb/N0 points "
+                      f"(same code, decoder and parameters), FP32 mode, {total_time:.1f} s"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the decode shards by frames and needs no "
+              "collective (see DESIGN.md), but only N=1 is run here", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1911_08868_amd as pbp
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    code = pbp.Code(N, K, CRC_W, CRC_POLY, DESIGN_DB)
+    F = args.frames
+    llrs, msgs = make_inputs(pbp, code, F, torch)
+    log(f"inputs ready: {len(SNRS)} x {F} frames")
+    outs = [(torch.empty((F, K_MSG), dtype=torch.uint8, device="cuda"),
+             torch.empty(F, dtype=torch.int32, device="cuda"),
+             torch.empty(F, dtype=torch.uint8, device="cuda")) for _ in SNRS]
+    bp = pbp.BPParams(max_iter=MAX_ITER, stop=pbp.STOP_CRC, it_min=IT_MIN)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=PP_K, period_T=PP_T, pool_Q=PP_Q, seed=PP_SEED)
+
+    for w in range(args.warmup):
+        run_decode_set(pbp, code, llrs, outs, bp, pp, torch)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1} done")
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in SNRS] for _ in range(args.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for s in range(args.steps):
+        run_decode_set(pbp, code, llrs, outs, bp, pp, torch, events=ev[s])
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {wall:.2f} s")
+    total_ms = start.elapsed_time(end)
+    ms_per_step = total_ms / args.steps
+    bits_per_step = len(SNRS) * F * K_MSG
+    value = bits_per_step / (ms_per_step / 1e3) / 1e9
+
+    # per-launch durations of the decode kernel and its algorithmic work
+    per_snr = []
+    launch_ms = 0.0
+    ops_total = 0.0
+    for si, snr in enumerate(SNRS):
+        msg_hat, iters, ok = outs[si]
+        d = sum(ev[s][si][0].elapsed_time(ev[s][si][1]) for s in range(args.steps)) / args.steps
+        ops = alg_ops(iters)
+        fer = (msg_hat != msgs[si]).any(1).double().mean().item()
+        per_snr.append({"ebn0_db": snr, "ms": round(d, 3),
+                        "gbit_s": round(F * K_MSG / (d / 1e3) / 1e9, 3),
+                        "avg_iters": round(iters.double().mean().item(), 3),
+                        "fer": fer})
+        launch_ms += d
+        ops_total += ops
+    achieved = ops_total / (launch_ms / 1e3) / 1e12
+    it_total = sum(o[1].double().sum().item() for o in outs)
+    lds_bytes_per_it = 16 * 4 * N  # 4 group boundaries x (L,R written and read) x N x 4 B
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": "k_decode<n=10,k=4,rho=2>",
+            "ops_per_frame_iteration": 8 * 10 * N,
+            "launch_ms_avg": round(launch_ms / len(SNRS), 3),
+            "lds": {"bytes_per_frame_iteration": lds_bytes_per_it,
+                    "achieved_TBs": round(lds_bytes_per_it * it_total / (launch_ms / 1e3) / 1e12, 3),
+                    "peak_TBs": round(LDS_PEAK_TBS, 2)},
+            "source_hash": kernel_source_hash()}
+    prof = os.path.join(ROOT, "profiles", "k_decode_n1024_traffic.json")
+    if os.path.exists(prof):
+        try:
+            t = json.load(open(prof))
+            if t.get("source_hash") == roof["source_hash"]:
+                roof["traffic"] = t.get("bytes_per_launch")
+        except Exception:
+            pass
+
+    extras = {}
+    if not args.no_extras:
+        # plain BP and full permutation on the same frames (one pass each)
+        for name, ppx in (("plain_bp", pbp.PPParams()),
+                          ("full_permutation", pbp.PPParams(mode=pbp.PP_FULL, period_T=25,
+                                                            pool_Q=8, seed=PP_SEED))):
+            ox = [(torch.empty((F, K_MSG), dtype=torch.uint8, device="cuda"),
+                   torch.empty(F, dtype=torch.int32, device="cuda"),
+                   torch.empty(F, dtype=torch.uint8, device="cuda")) for _ in SNRS]
+            run_decode_set(pbp, code, llrs, ox, bp, ppx, torch)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            run_decode_set(pbp, code, llrs, ox, bp, ppx, torch)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            log(f"{name}: {ms:.1f} ms")
+            extras[name] = {"gbit_s": round(bits_per_step / (ms / 1e3) / 1e9, 3),
+                            "ms": round(ms, 2),
+                            "fer": [(o[0] != m).any(1).double().mean().item()
+                                    for o, m in zip(ox, msgs)],
+                            "avg_iters": [round(o[1].double().mean().item(), 3) for o in ox]}
+            del ox
+        try:
+            from paper_1911_08868_amd import workloads
+            extras.update(workloads.bench_extras(torch, pbp))
+        except (ImportError, AttributeError, NotImplementedError) as e:
+            extras["weighted_bp"] = None
+            extras["batched_mixed"] = None
+            extras["extras_note"] = f"not available: {e}"
+
+    out = {
+        "metric": "decoded Gbit/s (N=1024 R=1/2 PP-MT-BP) + weighted-BP fwd+bwd frames/s vs plain",
+        "value": round(value, 4), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "PP-MT-BP N=1024 K=496+CRC16 R=1/2, Eb/N0 1.5:0.25:3.5 dB, "
+                               f"{F} frames per point, last k=4 of 10 stages permuted every "
+                               "T=10 iterations from Q=8 trellises, max 200 iterations, CRC stop",
+                   "frames_per_step": len(SNRS) * F, "message_bits_per_frame": K_MSG},
+        "roofline": roof,
+        "per_ebn0": per_snr,
+        "wall_s_timed": round(wall, 3),
+    }
+    out.update(extras)
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
