@@ -697,9 +697,10 @@ done:
 /* Weighted (unrolled) BP and its reverse-mode derivative.
  *
  * Each check-node output of the unrolled decoder is scaled by a learnable
- * weight w[t][s-1][d][row]: t the iteration (0..T-1), s the stage position,
- * d = 0 for the L sweep and 1 for the R sweep, row the output row of the PE
- * output (j or jp).  With all weights 1 this is plain min-sum BP.  Frozen
+ * weight w[t][s-1][d][pos]: t the iteration (0..T-1), s the stage position,
+ * d = 0 for the L sweep and 1 for the R sweep, pos the position of the PE
+ * output's row (j or jp) in the drawing of the active trellis (bit s-1 of
+ * pos is the bit stage s uses); on the original graph pos is the row itself.  With all weights 1 this is plain min-sum BP.  Frozen
  * priors are the finite value 2^60 instead of +inf so that products with zero
  * derivatives stay zero.  No early stop.  The output LLR of row j is
  * o_j = L[n][j] + R[n][j] after the last L sweep.
@@ -720,6 +721,14 @@ typedef struct {
 } or_wbp_params;
 
 static double sgnb(double v) { return signbit(v) ? -1.0 : 1.0; }
+
+/* position of row j in the drawing of the graph with stage order e: bit s-1
+ * of the position is bit e[s-1] of j (the original graph draws row j at j) */
+static int32_t drawn_pos(int32_t j, const int8_t *e, int n) {
+    int32_t p = 0;
+    for (int s = 0; s < n; s++) p |= ((j >> e[s]) & 1) << s;
+    return p;
+}
 static double ms0(double x, double y) {
     double m = fmin(fabs(x), fabs(y));
     return ((signbit(x) != 0) != (signbit(y) != 0)) ? -m : m;
@@ -768,8 +777,9 @@ static void wbp_forward_frame(const wctx_t *w, const float *llr, const double *w
                 double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
                 double r1 = Rin_state[(size_t)s * N + j], r2 = Rin_state[(size_t)s * N + jp];
                 double a = rnd(fp32, l2 + r2);
-                L[(size_t)s * N + j] = rnd(fp32, wl[j] * ms0(l1, a));
-                L[(size_t)s * N + jp] = rnd(fp32, rnd(fp32, wl[jp] * ms0(r1, l1)) + l2);
+                const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                L[(size_t)s * N + j] = rnd(fp32, wl[pj] * ms0(l1, a));
+                L[(size_t)s * N + jp] = rnd(fp32, rnd(fp32, wl[pjp] * ms0(r1, l1)) + l2);
             }
         }
         /* R sweep: Rw level n is the prior; levels below are fresh */
@@ -783,8 +793,9 @@ static void wbp_forward_frame(const wctx_t *w, const float *llr, const double *w
                 double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
                 double r1 = Rw[(size_t)s * N + j], r2 = Rw[(size_t)s * N + jp];
                 double a = rnd(fp32, l2 + r2);
-                Rw[(size_t)(s - 1) * N + j] = rnd(fp32, wr[j] * ms0(r1, a));
-                Rw[(size_t)(s - 1) * N + jp] = rnd(fp32, rnd(fp32, wr[jp] * ms0(r1, l1)) + r2);
+                const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                Rw[(size_t)(s - 1) * N + j] = rnd(fp32, wr[pj] * ms0(r1, a));
+                Rw[(size_t)(s - 1) * N + jp] = rnd(fp32, rnd(fp32, wr[pjp] * ms0(r1, l1)) + r2);
             }
         }
         memcpy(Rnext, Rw, sizeof(double) * lvl);
@@ -896,9 +907,10 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
                     double a = rnd(p->fp32, l2 + r2);
                     double g1 = ms0(r1, a), g2 = ms0(r1, l1);
                     double go1 = gR[(size_t)(s - 1) * N + j], go2 = gR[(size_t)(s - 1) * N + jp];
-                    gwr[j] += go1 * g1;
-                    gwr[jp] += go2 * g2;
-                    double d1 = go1 * wr[j], d2 = go2 * wr[jp];
+                    const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                    gwr[pj] += go1 * g1;
+                    gwr[pjp] += go2 * g2;
+                    double d1 = go1 * wr[pj], d2 = go2 * wr[pjp];
                     double ga = 0.0;
                     if (fabs(r1) <= fabs(a)) gR[(size_t)s * N + j] += d1 * sgnb(a);
                     else ga += d1 * sgnb(r1);
@@ -922,9 +934,10 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
                     double a = rnd(p->fp32, l2 + r2);
                     double f1 = ms0(l1, a), f2 = ms0(r1, l1);
                     double go1 = gL[(size_t)s * N + j], go2 = gL[(size_t)s * N + jp];
-                    gwl[j] += go1 * f1;
-                    gwl[jp] += go2 * f2;
-                    double d1 = go1 * wl[j], d2 = go2 * wl[jp];
+                    const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                    gwl[pj] += go1 * f1;
+                    gwl[pjp] += go2 * f2;
+                    double d1 = go1 * wl[pj], d2 = go2 * wl[pjp];
                     double ga = 0.0;
                     if (fabs(l1) <= fabs(a)) gL[(size_t)(s - 1) * N + j] += d1 * sgnb(a);
                     else ga += d1 * sgnb(l1);

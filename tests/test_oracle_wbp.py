@@ -94,6 +94,9 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
                 R[lev] = torch.zeros(F, N, dtype=torch.float64)
         qcur = q
         order = pool_orders[q] if pool_orders is not None else list(range(n))
+        # weight index: the row's position in the drawing of the active trellis
+        pos = torch.tensor([sum(((j >> int(order[s])) & 1) << s for s in range(n))
+                            for j in range(N)])
         L = [Lc] + [None] * n
         for s in range(1, n + 1):
             b = int(order[s - 1])
@@ -103,9 +106,9 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
             r1, r2 = R[s][:, top], R[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
             out = out.index_put((torch.arange(F)[:, None], top[None, :]),
-                                w[t, s - 1, 0, top] * ms(l1, l2 + r2))
+                                w[t, s - 1, 0, pos[top]] * ms(l1, l2 + r2))
             out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
-                                w[t, s - 1, 0, bot] * ms(r1, l1) + l2)
+                                w[t, s - 1, 0, pos[bot]] * ms(r1, l1) + l2)
             L[s] = out
         if t == T - 1:
             return L[n] + R[n]
@@ -119,9 +122,9 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
             r1, r2 = newR[s][:, top], newR[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
             out = out.index_put((torch.arange(F)[:, None], top[None, :]),
-                                w[t, s - 1, 1, top] * ms(r1, l2 + r2))
+                                w[t, s - 1, 1, pos[top]] * ms(r1, l2 + r2))
             out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
-                                w[t, s - 1, 1, bot] * ms(r1, l1) + r2)
+                                w[t, s - 1, 1, pos[bot]] * ms(r1, l1) + r2)
             newR[s - 1] = out
         R = newR
 
