@@ -699,8 +699,10 @@ done:
  * Each check-node output of the unrolled decoder is scaled by a learnable
  * weight w[t][s-1][d][pos]: t the iteration (0..T-1), s the stage position,
  * d = 0 for the L sweep and 1 for the R sweep, pos the position of the PE
- * output's row (j or jp) in the drawing of the active trellis (bit s-1 of
- * pos is the bit stage s uses); on the original graph pos is the row itself.  With all weights 1 this is plain min-sum BP.  Frozen
+ * output's row (j or jp).  Stages outside the permuted range keep their rows,
+ * so pos = row there; inside the permuted range pos is the row's position in
+ * the drawing of the active trellis (bit s-1 of pos is the bit stage s uses).
+ * On the original graph pos is the row itself.  With all weights 1 this is plain min-sum BP.  Frozen
  * priors are the finite value 2^60 instead of +inf so that products with zero
  * derivatives stay zero.  No early stop.  The output LLR of row j is
  * o_j = L[n][j] + R[n][j] after the last L sweep.
@@ -728,6 +730,11 @@ static int32_t drawn_pos(int32_t j, const int8_t *e, int n) {
     int32_t p = 0;
     for (int s = 0; s < n; s++) p |= ((j >> e[s]) & 1) << s;
     return p;
+}
+
+/* weight position of row j at stage s (1-based) under order e */
+static int32_t weight_pos(int32_t j, const int8_t *e, int n, int s, int k_perm) {
+    return (k_perm > 0 && s > n - k_perm) ? drawn_pos(j, e, n) : j;
 }
 static double ms0(double x, double y) {
     double m = fmin(fabs(x), fabs(y));
@@ -766,6 +773,7 @@ static void wbp_forward_frame(const wctx_t *w, const float *llr, const double *w
         double *Rnext = Rs + (size_t)(t + 1) * lvl;
         double *Rw = Rsweep + (size_t)t * lvl; /* R values produced by this R sweep */
         const int8_t *ord = w->pool + (size_t)wbp_order_at(w, t) * n;
+        const int kperm = (w->p->pp_mode == 0) ? w->p->k : 0;
         for (size_t i = 0; i < lvl; i++) L[i] = 0.0;
         for (int32_t j = 0; j < N; j++) L[j] = (double)llr[j];
         for (int s = 1; s <= n; s++) {
@@ -777,7 +785,7 @@ static void wbp_forward_frame(const wctx_t *w, const float *llr, const double *w
                 double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
                 double r1 = Rin_state[(size_t)s * N + j], r2 = Rin_state[(size_t)s * N + jp];
                 double a = rnd(fp32, l2 + r2);
-                const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
                 L[(size_t)s * N + j] = rnd(fp32, wl[pj] * ms0(l1, a));
                 L[(size_t)s * N + jp] = rnd(fp32, rnd(fp32, wl[pjp] * ms0(r1, l1)) + l2);
             }
@@ -793,7 +801,7 @@ static void wbp_forward_frame(const wctx_t *w, const float *llr, const double *w
                 double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
                 double r1 = Rw[(size_t)s * N + j], r2 = Rw[(size_t)s * N + jp];
                 double a = rnd(fp32, l2 + r2);
-                const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
                 Rw[(size_t)(s - 1) * N + j] = rnd(fp32, wr[pj] * ms0(r1, a));
                 Rw[(size_t)(s - 1) * N + jp] = rnd(fp32, rnd(fp32, wr[pjp] * ms0(r1, l1)) + r2);
             }
@@ -881,6 +889,7 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
             const double *Rin_state = Rs + (size_t)t * lvl;
             const double *Rsw = Rw + (size_t)t * lvl;
             const int8_t *ord = pool + (size_t)wbp_order_at(&w, t) * n;
+            const int kperm = (p->pp_mode == 0) ? p->k : 0;
             /* an event after iteration t reset the inner levels: nothing of
              * iteration t reaches iteration t+1 through them                 */
             if (t + 1 < T && p->pp_mode == 0 && pq > 1 &&
@@ -907,7 +916,7 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
                     double a = rnd(p->fp32, l2 + r2);
                     double g1 = ms0(r1, a), g2 = ms0(r1, l1);
                     double go1 = gR[(size_t)(s - 1) * N + j], go2 = gR[(size_t)(s - 1) * N + jp];
-                    const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                    const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
                     gwr[pj] += go1 * g1;
                     gwr[pjp] += go2 * g2;
                     double d1 = go1 * wr[pj], d2 = go2 * wr[pjp];
@@ -934,7 +943,7 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
                     double a = rnd(p->fp32, l2 + r2);
                     double f1 = ms0(l1, a), f2 = ms0(r1, l1);
                     double go1 = gL[(size_t)s * N + j], go2 = gL[(size_t)s * N + jp];
-                    const int32_t pj = drawn_pos(j, ord, n), pjp = drawn_pos(jp, ord, n);
+                    const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
                     gwl[pj] += go1 * f1;
                     gwl[pjp] += go2 * f2;
                     double d1 = go1 * wl[pj], d2 = go2 * wl[pjp];

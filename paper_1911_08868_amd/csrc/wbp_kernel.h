@@ -1,0 +1,590 @@
+// wbp_kernel.h -- weighted (unrolled) BP: forward with message checkpoints and
+// the hand-written adjoint (gfx950).
+//
+// Each check-node output of iteration t, stage s, sweep d (0 = L, 1 = R) is
+// scaled by w[t][s-1][d][pos], pos the output's position in the drawing of the
+// active trellis -- the row index the relabelled kernels already work in.
+// Frozen priors are the finite 2^60 so that zero adjoints times huge messages
+// stay zero.  There is no early stop; the output is o = L + R on level n+1
+// after the last L sweep, so the last R sweep is never run.
+//
+// Layout and thread map are those of the decode kernels (bp_core.h); a
+// workgroup holds S frames in lock step without refill (every frame runs T
+// iterations).  The forward pass stores the R state entering each iteration
+// t >= 1 (levels 1..n-1, (n-1) N floats per frame) in the thread's register
+// order, so stores and loads are coalesced across threads.
+//
+// The adjoint walks the iterations backwards.  For iteration t it reloads the
+// entering R state, recomputes the L sweep (keeping every L level) and the R
+// sweep (keeping every R level), then runs the reverse of the R sweep over the
+// groups bottom to top and the reverse of the L sweep top to bottom.  Adjoints
+// of the two boundary messages cross groups through LDS like the messages.
+// Min-sum derivative: for g = sgn(x) sgn(y) min(|x|,|y|), if |x| <= |y| then
+// dg/dx = sgn(y), else dg/dy = sgn(x) (ties route to the first argument).
+// Weight gradients of each iteration are staged per frame in LDS, summed over
+// the workgroup's frames in slot order and written as one partial per
+// workgroup; a second kernel sums the partials in workgroup order, so the
+// result does not depend on scheduling.
+#pragma once
+
+#include "bp_core.h"
+
+namespace pbp {
+
+constexpr float kWbpPrior = 1152921504606846976.0f;  // 2^60
+
+struct WbpArgs {
+    const float *llr;
+    int64_t F;
+    const float *w;        // [T][n][2][N]
+    int32_t T;
+    float *out;            // [F][N] forward output
+    const float *gout;     // [F][N] adjoint of the output
+    float *ckpt;           // [F][T-1][(n-1) N]
+    float *partial;        // [gridDim][T][n][2][N]
+    const int32_t *meta;   // per-row code table (frozen = -2)
+    int32_t Tev, Q;
+    int8_t orders[8][16];
+};
+
+__device__ __forceinline__ float ms0(float x, float y) { return cnode<false>(x, y, 1.f); }
+__device__ __forceinline__ float sgnf(float v) { return (__float_as_uint(v) >> 31) ? -1.f : 1.f; }
+
+template <class P>
+struct WbpLds {
+    // per slot: L/R ping-pong (4N), adjoint handoffs gR/gL (4N), staged weight
+    // gradients (2 n N); then the pool orders
+    static constexpr size_t per_slot = (size_t)(8 + 2 * P::n) * P::N * sizeof(float);
+    static constexpr size_t bytes(int S) { return (size_t)S * per_slot + 8 * 16; }
+};
+
+template <int NLOG, int RHO>
+constexpr int wbp_launch_bound() {
+    return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
+}
+
+// register order of the persistent R state (checkpoint layout)
+template <class P>
+struct RState {
+    static constexpr int NREG = (P::n - 1) * P::ROWS;
+    template <class Fn>
+    __device__ static __forceinline__ void each(Regs<P> &st, Fn &&fn) {
+        int k = 0;
+        sfor<0, P::G>([&](auto g) {
+            sfor<0, P::size(g) - 1>([&](auto l) {
+                sfor<0, P::ROWS>([&](auto i) { fn(st.Rint[g][l][i], k); ++k; });
+            });
+            if constexpr (g < P::G - 1) sfor<0, P::ROWS>([&](auto i) { fn(st.Rtop[g][i], k); ++k; });
+        });
+    }
+};
+
+// ---- forward passes with weights -------------------------------------------
+// wg points at the weights of this iteration, offset by the thread's row base
+// of group g; weight of stage-local sl, sweep d, register i:
+// wg[((lo + sl) * 2 + d) * N + off(i)]
+template <class P, int g>
+__device__ __forceinline__ void wgroup_L(const float (&lbot)[P::ROWS], float (&lint)[P::RI][P::ROWS],
+                                         const float (&rint)[P::RI][P::ROWS],
+                                         const float (&rtop)[P::ROWS], float (&out)[P::ROWS],
+                                         const float *wg) {
+    constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
+    float cur[ROWS];
+    sfor<0, ROWS>([&](auto i) { cur[i] = lbot[i]; });
+    sfor<0, r>([&](auto sl) {
+        float wv[ROWS];
+        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 0) * N + GMap<P, g>::off(i)]; });
+        float nxt[ROWS];
+        sfor<0, ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float r1, r2;
+                if constexpr (sl + 1 < r) { r1 = rint[sl][i]; r2 = rint[sl][ip]; }
+                else { r1 = rtop[i]; r2 = rtop[ip]; }
+                const float l1 = cur[i], l2 = cur[ip];
+                nxt[i] = wv[i] * ms0(l1, l2 + r2);
+                nxt[ip] = wv[ip] * ms0(r1, l1) + l2;
+            }
+        });
+        if constexpr (sl + 1 < r) sfor<0, ROWS>([&](auto i) { lint[sl][i] = nxt[i]; });
+        sfor<0, ROWS>([&](auto i) { cur[i] = nxt[i]; });
+    });
+    sfor<0, ROWS>([&](auto i) { out[i] = cur[i]; });
+}
+
+template <class P, int g>
+__device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
+                                         float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
+                                         float (&out)[P::ROWS], const float *wg) {
+    constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
+    float cur[ROWS];
+    sfor<0, ROWS>([&](auto i) { cur[i] = rtop[i]; });
+    sfor<0, r>([&](auto k) {
+        constexpr int sl = r - 1 - k;
+        float wv[ROWS];
+        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 1) * N + GMap<P, g>::off(i)]; });
+        float nxt[ROWS];
+        sfor<0, ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float l1, l2;
+                if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
+                else { l1 = lbot[i]; l2 = lbot[ip]; }
+                const float r1 = cur[i], r2 = cur[ip];
+                nxt[i] = wv[i] * ms0(r1, l2 + r2);
+                nxt[ip] = wv[ip] * ms0(r1, l1) + r2;
+            }
+        });
+        if constexpr (sl > 0) sfor<0, ROWS>([&](auto i) { rint[sl - 1][i] = nxt[i]; });
+        sfor<0, ROWS>([&](auto i) { cur[i] = nxt[i]; });
+    });
+    sfor<0, ROWS>([&](auto i) { out[i] = cur[i]; });
+}
+
+// ---- reverse passes ------------------------------------------------------
+// Reverse of the weighted R pass of group g.  gbot: adjoint of the R message
+// this group produces on its bottom level.  gstate: adjoint, from the next
+// iteration, of the R messages it produces on its interior levels.  Adds the
+// adjoints of the L messages it read into glint/glbot, returns in gtop the
+// adjoint of the R message it read on its top level, and stages the weight
+// gradients (sweep 1) in gw.
+template <class P, int g>
+__device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
+                                            const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
+                                            const float (&gbot)[P::ROWS], const float (&gstate)[P::RI][P::ROWS],
+                                            float (&glint)[P::RI][P::ROWS], float (&glbot)[P::ROWS],
+                                            float (&gtop)[P::ROWS], const float *wg, float *gw, int rowbase) {
+    constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
+    float gacc[P::RI][ROWS];
+    sfor<0, r - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { gacc[l][i] = gstate[l][i]; }); });
+    sfor<0, ROWS>([&](auto i) { gtop[i] = 0.f; });
+    sfor<0, r>([&](auto sl) {
+        float go[ROWS];
+        if constexpr (sl == 0) sfor<0, ROWS>([&](auto i) { go[i] = gbot[i]; });
+        else sfor<0, ROWS>([&](auto i) { go[i] = gacc[sl - 1][i]; });
+        float wv[ROWS];
+        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 1) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float r1, r2, l1, l2;
+                if constexpr (sl + 1 < r) { r1 = rsw[sl][i]; r2 = rsw[sl][ip]; }
+                else { r1 = rtopsw[i]; r2 = rtopsw[ip]; }
+                if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
+                else { l1 = lbot[i]; l2 = lbot[ip]; }
+                const float a = l2 + r2;
+                const float g1 = ms0(r1, a), g2 = ms0(r1, l1);
+                gw[((lo + sl) * 2 + 1) * N + rowbase + GMap<P, g>::off(i)] = go[i] * g1;
+                gw[((lo + sl) * 2 + 1) * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * g2;
+                const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
+                float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
+                if (__builtin_fabsf(r1) <= __builtin_fabsf(a)) {
+                    gr1 = d1 * sgnf(a);
+                } else {
+                    const float ga = d1 * sgnf(r1);
+                    gl2 = ga;
+                    gr2 = ga;
+                }
+                if (__builtin_fabsf(r1) <= __builtin_fabsf(l1)) gr1 += d2 * sgnf(l1);
+                else gl1 = d2 * sgnf(r1);
+                gr2 += go[ip];
+                if constexpr (sl + 1 < r) { gacc[sl][i] += gr1; gacc[sl][ip] += gr2; }
+                else { gtop[i] += gr1; gtop[ip] += gr2; }
+                if constexpr (sl > 0) { glint[sl - 1][i] += gl1; glint[sl - 1][ip] += gl2; }
+                else { glbot[i] += gl1; glbot[ip] += gl2; }
+            }
+        });
+    });
+}
+
+// Reverse of the weighted L pass of group g.  gtop: adjoint of the L message
+// it produced on its top level; glint: adjoints (already holding the R-sweep
+// contributions) of its interior L messages.  Adds to glbot, adds the
+// adjoints of the entering R state it read into gsint/gstop, stages the
+// weight gradients (sweep 0).
+template <class P, int g, bool TOPPRIOR>
+__device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
+                                            const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
+                                            const float (&gtop)[P::ROWS], float (&glint)[P::RI][P::ROWS],
+                                            float (&glbot)[P::ROWS], float (&gsint)[P::RI][P::ROWS],
+                                            float (&gstop)[P::ROWS], const float *wg, float *gw, int rowbase) {
+    constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
+    sfor<0, r>([&](auto k) {
+        constexpr int sl = r - 1 - k;
+        float go[ROWS];
+        if constexpr (sl == r - 1) sfor<0, ROWS>([&](auto i) { go[i] = gtop[i]; });
+        else sfor<0, ROWS>([&](auto i) { go[i] = glint[sl][i]; });
+        float wv[ROWS];
+        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 0) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) {
+            constexpr int b = 1 << sl;
+            if constexpr ((i & b) == 0) {
+                constexpr int ip = i | b;
+                float r1, r2, l1, l2;
+                if constexpr (sl + 1 < r) { r1 = rint[sl][i]; r2 = rint[sl][ip]; }
+                else { r1 = rtop[i]; r2 = rtop[ip]; }
+                if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
+                else { l1 = lbot[i]; l2 = lbot[ip]; }
+                const float a = l2 + r2;
+                const float f1 = ms0(l1, a), f2 = ms0(r1, l1);
+                gw[((lo + sl) * 2 + 0) * N + rowbase + GMap<P, g>::off(i)] = go[i] * f1;
+                gw[((lo + sl) * 2 + 0) * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * f2;
+                const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
+                float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
+                if (__builtin_fabsf(l1) <= __builtin_fabsf(a)) {
+                    gl1 = d1 * sgnf(a);
+                } else {
+                    const float ga = d1 * sgnf(l1);
+                    gl2 = ga;
+                    gr2 = ga;
+                }
+                if (__builtin_fabsf(r1) <= __builtin_fabsf(l1)) gr1 = d2 * sgnf(l1);
+                else gl1 += d2 * sgnf(r1);
+                gl2 += go[ip];
+                if constexpr (sl > 0) { glint[sl - 1][i] += gl1; glint[sl - 1][ip] += gl2; }
+                else { glbot[i] += gl1; glbot[ip] += gl2; }
+                if constexpr (sl + 1 < r) { gsint[sl][i] += gr1; gsint[sl][ip] += gr2; }
+                else if constexpr (!TOPPRIOR) { gstop[i] += gr1; gstop[ip] += gr2; }
+            }
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
+template <int NLOG, int KP, int RHO>
+__global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(WbpArgs a) {
+    using P = Plan<NLOG, KP, RHO>;
+    constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG, GB = P::GB;
+    constexpr bool MAPPED = (KP > 0 && KP < NLOG);
+    constexpr int LOWBITS = NLOG - KP;
+    constexpr int NREG = RState<P>::NREG;
+    const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
+    const int64_t frame = (int64_t)blockIdx.x * S + slot;
+    const bool active = frame < a.F;
+    extern __shared__ __align__(16) float smem[];
+    float *const buf = smem + (size_t)slot * (WbpLds<P>::per_slot / sizeof(float));
+    int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * (WbpLds<P>::per_slot / sizeof(float)));
+    if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
+    __syncthreads();
+
+    Regs<P> st;
+    int baddr[ROWS], toprow[ROWS];
+    uint32_t frozen_bits = 0;
+    int q = 0;
+    auto maps = [&](int qq) {
+        const int8_t *e = ords + qq * 16;
+        const int base = GMap<P, G - 1>::base(t);
+        frozen_bits = 0;
+        sfor<0, ROWS>([&](auto i) {
+            const int p = base + GMap<P, G - 1>::off(i);
+            const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+            toprow[i] = j;
+            frozen_bits |= (a.meta[j] == -2 ? 1u : 0u) << i;
+        });
+        if constexpr (MAPPED) {
+            const int bb = GMap<P, GB>::base(t);
+            sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
+        }
+        const float *src = a.llr + frame * N;
+        const int b0 = GMap<P, 0>::base(t);
+        if constexpr (KP == NLOG) {
+            sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[relabel_to_row(b0 + GMap<P, 0>::off(i), e, n, 0)]; });
+        } else {
+            sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[b0 + GMap<P, 0>::off(i)]; });
+        }
+    };
+    sfor<0, G>([&](auto g) {
+        sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
+        sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
+    });
+    if (active) maps(0);
+
+    for (int it = 0; it < a.T; ++it) {
+        if constexpr (KP > 0) {
+            const int qn = a.Q > 1 ? (it / a.Tev) % a.Q : 0;
+            if (qn != q) {
+                q = qn;
+                sfor<GB, G>([&](auto g) {
+                    sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
+                    if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
+                });
+                if (active) maps(q);
+            }
+        }
+        if (it > 0 && active) {
+            float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS + t;
+            RState<P>::each(st, [&](float &v, int k) { ck[(int64_t)k * TPS] = v; });
+        }
+        const float *wt = a.w + (int64_t)it * n * 2 * N;
+        sfor<0, G - 1>([&](auto g) {
+            if (active) {
+                if constexpr (g > 0) {
+                    const float *lb = buf + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
+                    else {
+                        const int base = GMap<P, g>::base(t);
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+                    }
+                }
+                float out[ROWS];
+                const int base = GMap<P, g>::base(t);
+                wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
+                float *lt = buf + ((g + 1) & 1) * N;
+                sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+            }
+            __syncthreads();
+        });
+        if (active) {
+            if constexpr (G > 1) {
+                const float *lb = buf + ((G - 1) & 1) * N;
+                if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+                else {
+                    const int base = GMap<P, G - 1>::base(t);
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
+                }
+            }
+            float prior[ROWS];
+            sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
+            const int base = GMap<P, G - 1>::base(t);
+            wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
+            if (it == a.T - 1) {
+                sfor<0, ROWS>([&](auto i) { a.out[frame * N + toprow[i]] = st.Ltop[i] + prior[i]; });
+            } else {
+                float rb[ROWS];
+                wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, rb, wt + base);
+                if constexpr (G > 1) {
+                    float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                    if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                    else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
+                }
+            }
+        }
+        __syncthreads();
+        if (it == a.T - 1) break;
+        sfor<0, G - 1>([&](auto k) {
+            constexpr int g = G - 2 - k;
+            if (active) {
+                const int base = GMap<P, g>::base(t);
+                const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
+                sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rs[base + GMap<P, g>::off(i)]; });
+                float rb[ROWS];
+                wgroup_R<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], rb, wt + base);
+                if constexpr (g > 0) {
+                    float *rt = buf + 2 * N + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                    else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                }
+            }
+            __syncthreads();
+        });
+    }
+}
+
+template <int NLOG, int KP, int RHO>
+__global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(WbpArgs a) {
+    using P = Plan<NLOG, KP, RHO>;
+    constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG, GB = P::GB;
+    constexpr bool MAPPED = (KP > 0 && KP < NLOG);
+    constexpr int LOWBITS = NLOG - KP;
+    constexpr int NREG = RState<P>::NREG;
+    constexpr int RI = P::RI;
+    const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
+    const int64_t frame = (int64_t)blockIdx.x * S + slot;
+    const bool active = frame < a.F;
+    constexpr size_t PS = WbpLds<P>::per_slot / sizeof(float);
+    extern __shared__ __align__(16) float smem[];
+    float *const buf = smem + (size_t)slot * PS;     // L0 L1 R0 R1 gR0 gR1 gL0 gL1 | gw[n][2][N]
+    float *const gw = buf + 8 * N;
+    int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * PS);
+    if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
+    __syncthreads();
+
+    Regs<P> st;                         // entering R state and this iteration's L messages
+    float Rsw[G][RI][ROWS], Rtsw[G][ROWS];  // R messages of this iteration's R sweep
+    float gsi[G][RI][ROWS], gst[G][ROWS];   // adjoint of the R state leaving the iteration
+    float gli[G][RI][ROWS], glb[G][ROWS];   // adjoints of the L messages
+    int baddr[ROWS], toprow[ROWS];
+    uint32_t frozen_bits = 0;
+    sfor<0, G>([&](auto g) {
+        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
+        sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+    });
+    auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
+
+    for (int it = a.T - 1; it >= 0; --it) {
+        const int q = order_at(it);
+        const float *wt = a.w + (int64_t)it * n * 2 * N;
+        const bool lastit = (it == a.T - 1);
+        if (active) {
+            const int8_t *e = ords + q * 16;
+            const int base = GMap<P, G - 1>::base(t);
+            frozen_bits = 0;
+            sfor<0, ROWS>([&](auto i) {
+                const int p = base + GMap<P, G - 1>::off(i);
+                const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+                toprow[i] = j;
+                frozen_bits |= (a.meta[j] == -2 ? 1u : 0u) << i;
+            });
+            if constexpr (MAPPED) {
+                const int bb = GMap<P, GB>::base(t);
+                sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
+            }
+            const float *src = a.llr + frame * N;
+            const int b0 = GMap<P, 0>::base(t);
+            if constexpr (KP == NLOG) {
+                sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[relabel_to_row(b0 + GMap<P, 0>::off(i), e, n, 0)]; });
+            } else {
+                sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[b0 + GMap<P, 0>::off(i)]; });
+            }
+            // entering R state
+            if (it == 0) {
+                RState<P>::each(st, [&](float &v, int k) { v = 0.f; });
+            } else {
+                const float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS + t;
+                RState<P>::each(st, [&](float &v, int k) { v = ck[(int64_t)k * TPS]; });
+            }
+            // a trellis switch after this iteration reset the inner levels of
+            // the permuted range: nothing flows back through them
+            if constexpr (KP > 0) {
+                if (!lastit && order_at(it + 1) != q) {
+                    sfor<GB, G>([&](auto g) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
+                        if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+                    });
+                }
+            }
+            sfor<0, G>([&](auto g) {
+                sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[g][l][i] = 0.f; }); });
+                sfor<0, ROWS>([&](auto i) { glb[g][i] = 0.f; });
+            });
+        }
+        // ---- recompute the L sweep ----
+        sfor<0, G - 1>([&](auto g) {
+            if (active) {
+                const int base = GMap<P, g>::base(t);
+                if constexpr (g > 0) {
+                    const float *lb = buf + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
+                    else sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+                }
+                float out[ROWS];
+                wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
+                float *lt = buf + ((g + 1) & 1) * N;
+                sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+            }
+            __syncthreads();
+        });
+        float prior[ROWS];
+        sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
+        if (active) {
+            const int base = GMap<P, G - 1>::base(t);
+            if constexpr (G > 1) {
+                const float *lb = buf + ((G - 1) & 1) * N;
+                if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+                else sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
+            }
+            wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
+            // ---- recompute the R sweep, keeping every level ----
+            if (!lastit) {
+                sfor<0, ROWS>([&](auto i) { Rtsw[G - 1][i] = prior[i]; });
+                float rb[ROWS];
+                wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], Rsw[G - 1], prior, rb, wt + base);
+                if constexpr (G > 1) {
+                    float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                    if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                    else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
+                }
+            }
+        }
+        __syncthreads();
+        if (!lastit) {
+            sfor<0, G - 1>([&](auto k) {
+                constexpr int g = G - 2 - k;
+                if (active) {
+                    const int base = GMap<P, g>::base(t);
+                    const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
+                    sfor<0, ROWS>([&](auto i) { Rtsw[g][i] = rs[base + GMap<P, g>::off(i)]; });
+                    float rb[ROWS];
+                    wgroup_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], rb, wt + base);
+                    if constexpr (g > 0) {
+                        float *rt = buf + 2 * N + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                        else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                    }
+                }
+                __syncthreads();
+            });
+            // ---- reverse of the R sweep: groups bottom to top ----
+            sfor<0, G>([&](auto g) {
+                if (active) {
+                    const int base = GMap<P, g>::base(t);
+                    float gb[ROWS];
+                    if constexpr (g == 0) {
+                        sfor<0, ROWS>([&](auto i) { gb[i] = 0.f; });
+                    } else {
+                        const float *src = buf + 4 * N + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { gb[i] = src[baddr[i]]; });
+                        else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
+                    }
+                    float gtop[ROWS];
+                    rev_group_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
+                                      wt + base, gw, base);
+                    if constexpr (g < G - 1) {
+                        float *dst = buf + 4 * N + ((g + 1) & 1) * N;
+                        sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
+                    }
+                }
+                __syncthreads();
+            });
+        }
+        // the new state adjoint comes only from the reverse L sweep
+        sfor<0, G>([&](auto g) {
+            sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
+            sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+        });
+        // ---- reverse of the L sweep: groups top to bottom ----
+        sfor<0, G>([&](auto k) {
+            constexpr int g = G - 1 - k;
+            if (active) {
+                const int base = GMap<P, g>::base(t);
+                float gt[ROWS];
+                if constexpr (g == G - 1) {
+                    if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
+                    else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
+                    rev_group_L<P, g, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g], gsi[g],
+                                            gst[g], wt + base, gw, base);
+                } else {
+                    const float *src = buf + 6 * N + ((g + 1) & 1) * N;
+                    sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
+                    rev_group_L<P, g, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g], glb[g],
+                                             gsi[g], gst[g], wt + base, gw, base);
+                }
+                if constexpr (g > 0) {
+                    float *dst = buf + 6 * N + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { dst[baddr[i]] = glb[g][i]; });
+                    else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[g][i]; });
+                }
+            }
+            __syncthreads();
+        });
+        // ---- weight gradients of iteration it: sum over this workgroup's frames
+        {
+            float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+            for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
+                float v = 0.f;
+                const bool rsweep = ((idx / N) & 1) != 0;
+                if (!(lastit && rsweep)) {
+                    for (int s = 0; s < S; ++s)
+                        if ((int64_t)blockIdx.x * S + s < a.F) v += smem[(size_t)s * PS + 8 * N + idx];
+                }
+                part[idx] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace pbp

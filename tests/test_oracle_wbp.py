@@ -94,14 +94,17 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
                 R[lev] = torch.zeros(F, N, dtype=torch.float64)
         qcur = q
         order = pool_orders[q] if pool_orders is not None else list(range(n))
-        # weight index: the row's position in the drawing of the active trellis
-        pos = torch.tensor([sum(((j >> int(order[s])) & 1) << s for s in range(n))
-                            for j in range(N)])
+        # weight index: the row for stages outside the permuted range, the row's
+        # position in the drawing of the active trellis inside it
+        drawn = torch.tensor([sum(((j >> int(order[s])) & 1) << s for s in range(n))
+                              for j in range(N)])
+        ident = torch.arange(N)
         L = [Lc] + [None] * n
         for s in range(1, n + 1):
             b = int(order[s - 1])
             top = torch.tensor([j for j in range(N) if not (j >> b) & 1])
             bot = top | (1 << b)
+            pos = drawn if (k and s > n - k) else ident
             l1, l2 = L[s - 1][:, top], L[s - 1][:, bot]
             r1, r2 = R[s][:, top], R[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
@@ -118,6 +121,7 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
             b = int(order[s - 1])
             top = torch.tensor([j for j in range(N) if not (j >> b) & 1])
             bot = top | (1 << b)
+            pos = drawn if (k and s > n - k) else ident
             l1, l2 = L[s - 1][:, top], L[s - 1][:, bot]
             r1, r2 = newR[s][:, top], newR[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
