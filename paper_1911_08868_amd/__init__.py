@@ -23,3 +23,5 @@ __all__ = [
     "encode", "bp_decode", "pp_mt_bp_decode", "decode_batched", "batched_workspace_bytes",
     "wbp_workspace_bytes", "wbp_forward", "wbp_backward",
 ]
+
+from . import wbp  # noqa: E402  (torch.autograd wrapper of the weighted kernels)

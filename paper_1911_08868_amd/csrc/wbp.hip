@@ -1,19 +1,159 @@
-// wbp.hip -- weighted (unrolled) BP forward and adjoint kernels.
-#include "internal.h"
+// wbp.hip -- weighted BP entry points: workspace sizing, validation, the
+// forward and adjoint launches and the deterministic reduction of the
+// per-workgroup weight-gradient partials.
+#include <cstring>
+
+#include "wbp_inst.h"
+
+namespace pbp {
+
+int run_wbp_n4(const WbpLaunch &);
+int run_wbp_n5(const WbpLaunch &);
+int run_wbp_n6(const WbpLaunch &);
+int run_wbp_n7(const WbpLaunch &);
+int run_wbp_n8(const WbpLaunch &);
+int run_wbp_n9(const WbpLaunch &);
+int run_wbp_n10(const WbpLaunch &);
+
+int launch_wbp_n(int n, const WbpLaunch &L) {
+    switch (n) {
+        case 4: return run_wbp_n4(L);
+        case 5: return run_wbp_n5(L);
+        case 6: return run_wbp_n6(L);
+        case 7: return run_wbp_n7(L);
+        case 8: return run_wbp_n8(L);
+        case 9: return run_wbp_n9(L);
+        case 10: return run_wbp_n10(L);
+        default: return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 1024");
+    }
+}
+
+// grad_w[i] = sum over workgroups g (in order) of partial[g][i]
+__global__ void __launch_bounds__(256) k_grad_reduce(const float *partial, int64_t groups, int64_t len,
+                                                     float *grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int64_t g = 0; g < groups; ++g) s += partial[g * len + i];
+    grad[i] = s;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WbpLayout {
+    size_t ckpt_bytes = 0, partial_bytes = 0, total = 0;
+    int slots = 0;
+    int64_t groups = 0;
+};
+
+static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
+    WbpLayout w;
+    w.slots = wbp_slots(c->n);
+    w.groups = (F + w.slots - 1) / w.slots;
+    w.ckpt_bytes = align256((size_t)F * (size_t)(T > 1 ? T - 1 : 0) * (size_t)(c->n - 1) * c->N * sizeof(float));
+    w.partial_bytes = align256((size_t)w.groups * T * c->n * 2 * (size_t)c->N * sizeof(float));
+    w.total = w.ckpt_bytes + w.partial_bytes;
+    return w;
+}
+
+size_t wbp_ws_bytes(const pc_code *c, int64_t F, int T) { return wbp_layout(c, F, T).total; }
+
+static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const float *d_w, int T,
+                      const pc_pp_params *pp, void *d_ws, size_t ws_bytes, WbpLaunch &L,
+                      WbpLayout &lay) {
+    if (!c) return fail(PC_EINVAL, "code is NULL");
+    if (c->n < 4 || c->n > 10) return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 1024");
+    if (T < 1) return fail(PC_EINVAL, "T_unroll must be >= 1");
+    if (F < 0) return fail(PC_EINVAL, "F < 0");
+    if (F > 0 && (!d_llr || !d_w)) return fail(PC_EINVAL, "null buffer");
+    lay = wbp_layout(c, F, T);
+    if (F > 0 && (!d_ws || ws_bytes < lay.total)) return fail(PC_ENOMEM, "workspace too small");
+    std::memset(&L.args, 0, sizeof(L.args));
+    int8_t orders[kMaxPool * kMaxLog] = {0};
+    int kp = 0, Q = 1, Tev = 1;
+    const int n = c->n;
+    if (pp && pp->mode != PC_PP_NONE) {
+        if (pp->mode != PC_PP_LASTK) return fail(PC_ENOTSUP, "weighted BP supports the fixed last-k schedule");
+        if (pp->k < 2 || pp->k > n) return fail(PC_EINVAL, "k must satisfy 2 <= k <= n");
+        if (pp->period_T < 1 || pp->pool_Q < 1 || pp->pool_Q > kMaxPool)
+            return fail(PC_EINVAL, "period T >= 1 and pool Q in 1..8");
+        Q = make_pool(n, pp->k, pp->pool_Q, pp->seed, orders);
+        if (Q < 0) return Q;
+        kp = Q > 1 ? pp->k : 0;
+        Tev = pp->period_T;
+        if (kp == n) return fail(PC_ENOTSUP, "weighted BP with full permutations is not built");
+    } else {
+        for (int s = 0; s < n; ++s) orders[s] = (int8_t)s;
+    }
+    WbpArgs &a = L.args;
+    a.llr = d_llr;
+    a.F = F;
+    a.w = d_w;
+    a.T = T;
+    a.ckpt = static_cast<float *>(d_ws);
+    a.partial = reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes);
+    a.meta = c->d.meta;
+    a.Tev = Tev;
+    a.Q = Q;
+    for (int q = 0; q < Q; ++q)
+        for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
+    L.kp = kp;
+    L.slots = lay.slots;
+    L.grid = (int)lay.groups;
+    return PC_OK;
+}
+
+}  // namespace pbp
 
 using namespace pbp;
 
 extern "C" {
+
 size_t wbp_workspace_bytes(const pc_code *code, int64_t F, int32_t T_unroll) {
-    (void)code; (void)F; (void)T_unroll;
-    return 0;
+    if (!code || F < 0 || T_unroll < 1) return 0;
+    return wbp_ws_bytes(code, F, T_unroll);
 }
-int wbp_forward(const pc_code *, const float *, int64_t, const float *, int32_t,
-                const pc_pp_params *, float *, void *, size_t, void *) {
-    return fail(PC_ENOTSUP, "weighted BP not built yet");
+
+int wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                int32_t T_unroll, const pc_pp_params *pp, float *d_out_llr, void *d_ws,
+                size_t ws_bytes, void *stream) {
+    WbpLaunch L;
+    WbpLayout lay;
+    int rc = wbp_common(code, d_llr, F, d_w, T_unroll, pp, d_ws, ws_bytes, L, lay);
+    if (rc) return rc;
+    if (F == 0) return PC_OK;
+    if (!d_out_llr) return fail(PC_EINVAL, "null output");
+    L.args.out = d_out_llr;
+    L.backward = false;
+    L.stream = static_cast<hipStream_t>(stream);
+    return launch_wbp_n(code->n, L);
 }
-int wbp_backward(const pc_code *, const float *, int64_t, const float *, int32_t,
-                 const pc_pp_params *, const float *, float *, void *, size_t, void *) {
-    return fail(PC_ENOTSUP, "weighted BP not built yet");
+
+int wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,
+                 int32_t T_unroll, const pc_pp_params *pp, const float *d_grad_out,
+                 float *d_grad_w, void *d_ws, size_t ws_bytes, void *stream) {
+    WbpLaunch L;
+    WbpLayout lay;
+    int rc = wbp_common(code, d_llr, F, d_w, T_unroll, pp, d_ws, ws_bytes, L, lay);
+    if (rc) return rc;
+    if (!d_grad_w) return fail(PC_EINVAL, "null gradient output");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int64_t len = (int64_t)T_unroll * code->n * 2 * code->N;
+    if (F == 0) {
+        hipError_t e = hipMemsetAsync(d_grad_w, 0, (size_t)len * sizeof(float), hs);
+        return e == hipSuccess ? PC_OK : hip_fail(e, "gradient clear");
+    }
+    if (!d_grad_out) return fail(PC_EINVAL, "null output adjoint");
+    L.args.gout = d_grad_out;
+    L.backward = true;
+    L.stream = hs;
+    rc = launch_wbp_n(code->n, L);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, hs,
+                       L.args.partial, lay.groups, len, d_grad_w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+    return PC_OK;
 }
-}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// wbp_inst.h -- launches of the weighted-BP kernels for one block length.
+#pragma once
+
+#include "internal.h"
+#include "wbp_kernel.h"
+
+namespace pbp {
+
+struct WbpLaunch {
+    WbpArgs args;
+    int kp = 0;
+    bool backward = false;
+    int slots = 0, grid = 0;
+    hipStream_t stream = nullptr;
+};
+
+// frames per workgroup of the weighted kernels for block length 2^n
+inline int wbp_slots(int n) {
+    const int tps = 1 << (n - 2);
+    return tps >= 256 ? 1 : 256 / tps;
+}
+
+template <int NLOG, int KP>
+int run_wbp(const WbpLaunch &L) {
+    using P = Plan<NLOG, KP, 2>;
+    const int S = L.slots;
+    const size_t lds = WbpLds<P>::bytes(S);
+    if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for weighted BP");
+    if (L.backward)
+        hipLaunchKernelGGL((k_wbp_bwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);
+    else
+        hipLaunchKernelGGL((k_wbp_fwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "weighted BP launch");
+    return PC_OK;
+}
+
+template <int NLOG>
+int run_wbp_n(const WbpLaunch &L) {
+    switch (L.kp) {
+        case 0: return run_wbp<NLOG, 0>(L);
+        case 2: if constexpr (NLOG > 2) return run_wbp<NLOG, 2>(L); break;
+        case 3: if constexpr (NLOG > 3) return run_wbp<NLOG, 3>(L); break;
+        case 4: if constexpr (NLOG > 4) return run_wbp<NLOG, 4>(L); break;
+        case 5: if constexpr (NLOG > 5) return run_wbp<NLOG, 5>(L); break;
+        default: break;
+    }
+    return fail(PC_ENOTSUP, "weighted BP supports permuted ranges k = 2..5 below n");
+}
+
+int launch_wbp_n(int n, const WbpLaunch &L);
+
+}  // namespace pbp

@@ -1,0 +1,120 @@
+"""GPU parity of weighted BP (forward and hand-written adjoint) against the
+oracle: forward outputs bit-exact against the FP32 oracle; weight gradients
+(FP32 accumulation) against the oracle's adjoint within a tolerance derived
+from FP32 summation; determinism across runs; the autograd wrapper."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pbp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1911_08868_amd as m
+    return m
+
+
+def _setup(orc, N, K, F, seed, snr=1.5, cw=0, poly=0):
+    oc = orc.construct(N, K, 2.5, cw, poly)
+    msg = synth.message_bits(seed, F, oc.K_msg)
+    u, x = orc.encode(oc, msg)
+    return oc, u, synth.awgn_llr(x, snr, oc.K_msg, seed=seed)
+
+
+def _gpu(pbp, oc, llr, w, T, pp, gout):
+    import torch
+    code = pbp.Code(oc.N, oc.K, oc.crc_width, oc.crc_poly, 2.5)
+    assert np.array_equal(code.info_idx, oc.info_idx)
+    d_llr = torch.from_numpy(llr).cuda()
+    d_w = torch.from_numpy(w.astype(np.float32)).cuda()
+    F = llr.shape[0]
+    ws = torch.empty(max(pbp.wbp_workspace_bytes(code, F, T), 1), dtype=torch.uint8, device="cuda")
+    out = torch.empty((F, oc.N), dtype=torch.float32, device="cuda")
+    pbp.wbp_forward(code, d_llr, d_w, pp, out, ws)
+    gw = torch.empty_like(d_w)
+    pbp.wbp_backward(code, d_llr, d_w, pp, torch.from_numpy(gout.astype(np.float32)).cuda(), gw, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), gw.cpu().numpy()
+
+
+def _grad_tol(ref):
+    # FP32 accumulation of O(F * n) terms in a different order than the FP64 oracle
+    return 2e-4 * max(1.0, float(np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("N,K,T,F,pp", [(16, 8, 2, 7, None), (16, 8, 3, 64, (2, 1, 2)),
+                                        (32, 16, 4, 33, (3, 2, 3)), (256, 144, 10, 96, None),
+                                        (256, 144, 10, 50, (4, 3, 8)), (64, 32, 5, 130, None),
+                                        (1024, 512, 3, 9, (5, 1, 8))])
+def test_weighted_forward_and_adjoint(orc, pbp, N, K, T, F, pp):
+    n = N.bit_length() - 1
+    oc, u, llr = _setup(orc, N, K, F, seed=N + T + F)
+    rng = np.random.default_rng(N * T)
+    w = rng.uniform(0.7, 1.3, (T, n, 2, N)).astype(np.float32).astype(np.float64)
+    gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
+    gout[:, oc.frozen.astype(bool)] = 0.0
+    if pp:
+        k, tev, Q = pp
+        opp = orc.WbpParams(pp_mode=orc.PP_LASTK, k=k, T_ev=tev, Q=Q, seed=7, fp32=True)
+        gpp = pbp.PPParams(mode=pbp.PP_LASTK, k=k, period_T=tev, pool_Q=Q, seed=7)
+    else:
+        opp = orc.WbpParams(fp32=True)
+        gpp = None
+    out, gw = _gpu(pbp, oc, llr, w, T, gpp, gout)
+    ref_out = orc.wbp_forward(oc, llr, w, opp)
+    assert np.array_equal(out.view(np.uint32), ref_out.astype(np.float32).view(np.uint32))
+    ref_gw, _ = orc.wbp_backward(oc, llr, w, opp, gout)
+    np.testing.assert_allclose(gw, ref_gw, rtol=0, atol=_grad_tol(ref_gw))
+    # the last R sweep never reaches the output
+    assert np.all(gw[T - 1, :, 1] == 0.0)
+
+
+def test_weighted_gradient_is_deterministic(orc, pbp):
+    oc, u, llr = _setup(orc, 256, 144, 300, seed=5)
+    rng = np.random.default_rng(1)
+    w = rng.uniform(0.8, 1.2, (6, 8, 2, 256))
+    g = rng.normal(size=(300, 256))
+    a = _gpu(pbp, oc, llr, w, 6, None, g)[1]
+    b = _gpu(pbp, oc, llr, w, 6, None, g)[1]
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_unit_weights_reproduce_decoder_soft_output(orc, pbp):
+    import torch
+    oc, u, llr = _setup(orc, 256, 144, 40, seed=9, snr=2.0, cw=16, poly=0x1021)
+    code = pbp.Code(256, 144, 16, 0x1021, 2.5)
+    T = 7
+    dec = pbp.wbp.WeightedBPDecoder(code, T)
+    out = dec(torch.from_numpy(llr).cuda()).detach().cpu().numpy()
+    msg, iters, ok, soft = pbp.bp_decode(code, torch.from_numpy(llr).cuda(),
+                                         pbp.BPParams(max_iter=T, stop=pbp.STOP_NONE), soft=True)
+    info = oc.info_idx
+    assert np.array_equal(out[:, info].view(np.uint32), soft.cpu().numpy()[:, info].view(np.uint32))
+
+
+def test_autograd_training_step(orc, pbp):
+    import torch
+    oc, u, llr = _setup(orc, 64, 32, 256, seed=11, snr=2.0)
+    code = pbp.Code(64, 32, 0, 0, 2.5)
+    dec = pbp.wbp.WeightedBPDecoder(code, 4)
+    x = torch.from_numpy(llr).cuda()
+    info = torch.from_numpy(oc.info_idx.astype(np.int64)).cuda()
+    ub = torch.from_numpy(u[:, oc.info_idx]).cuda()
+    loss = pbp.wbp.bce_on_information_bits(dec(x), ub, info)
+    loss.backward()
+    g = dec.weight.grad.detach().cpu().numpy().astype(np.float64)
+    # d loss / d o from the same BCE, then the oracle's adjoint
+    o = torch.from_numpy(orc.wbp_forward(oc, llr, np.ones((4, 6, 2, 64)), orc.WbpParams(fp32=True)))
+    o.requires_grad_(True)
+    lo = o[:, torch.from_numpy(oc.info_idx.astype(np.int64))]
+    uu = torch.from_numpy(u[:, oc.info_idx]).double()
+    l2 = (uu * torch.nn.functional.softplus(lo) + (1 - uu) * torch.nn.functional.softplus(-lo)).mean()
+    l2.backward()
+    ref, _ = orc.wbp_backward(oc, llr, np.ones((4, 6, 2, 64)), orc.WbpParams(fp32=True),
+                              o.grad.numpy())
+    np.testing.assert_allclose(g, ref, rtol=0, atol=_grad_tol(ref))
+    assert abs(loss.item() - l2.item()) < 1e-5 * max(1.0, abs(l2.item()))
