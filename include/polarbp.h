@@ -144,26 +144,31 @@ int pp_mt_bp_decode_ex(const pc_code *code, const float *d_llr, int64_t F,
                        const pc_launch_cfg *cfg, void *stream);
 
 /* Batched decoding of frames of mixed length and rate in one persistent
- * launch fed from a device work queue.  codes[0..n_codes) are codes built on
- * this device (n_codes <= 32, all with the same crc_width, N in [64, 1024]);
- * d_code_id int32 [F] selects each frame's code; d_llr_off int64 [F] is the
+ * launch fed from a device work queue.  codes[0..n_codes) (n_codes <= 32)
+ * are codes built on this device, each with N in [64, 1024] and a CRC;
+ * d_code_id int32 [F] selects each frame's code (a frame whose id is outside
+ * 0..n_codes-1 is skipped and its outputs are left untouched); d_llr_off int64 [F] is the
  * float offset of frame f's N LLRs in d_llr_pool; d_bits_off int64 [F] the
- * byte offset of its K - crc_width decided bits in d_bits_pool.  Frames are
- * taken from the queue in the order of d_order (int32 [F], a permutation of
- * 0..F-1, or NULL for 0..F-1).  d_iters, d_ok int32/uint8 [F] or NULL.
- * d_ws: device workspace of at least polar_batched_workspace_bytes(n_codes)
- * bytes, reset by the call itself (no memset needed; the call can be captured
- * into a HIP graph after one warm-up call has created the code tables).
- * cfgs: per log2(N) launch configuration indexed by n - 6 (4 entries), or
- * NULL.                                                                     */
-size_t polar_batched_workspace_bytes(int32_t n_codes);
+ * byte offset of its K - crc_width decided bits in d_bits_pool.  d_iters
+ * int32 [F] and d_ok uint8 [F] as in bp_decode, or NULL.  The stop test is
+ * the CRC (or none); pp is NULL / PC_PP_NONE or PC_PP_LASTK with k = 4 (the
+ * last 4 stages of every length), each length with its own pool drawn from
+ * the same seed.  Frames are bucketed by length on the device and decoded
+ * longest first; a slot whose frame stops takes the next frame of its
+ * length from the queue.  d_ws: device workspace of at least
+ * polar_batched_workspace_bytes(F) bytes; the call clears what it needs with
+ * its own kernels (no memset), so after one warm-up call on the device the
+ * whole call can be captured into a HIP graph and replayed with new frame
+ * data in the same buffers.  Overlapping calls must use different workspaces.
+ * cfg: rho (2 or 3), slots = 1 (256-thread workgroups) or 2 (512), grid
+ * (0 = as many workgroups as fit); NULL for the defaults.                   */
+size_t polar_batched_workspace_bytes(int64_t F);
 int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
                             const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
-                            const int32_t *d_order, const pc_bp_params *bp,
-                            const pc_pp_params *pp, uint8_t *d_bits_pool,
-                            const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok,
-                            void *d_ws, size_t ws_bytes, const pc_launch_cfg *cfgs,
-                            void *stream);
+                            const pc_bp_params *bp, const pc_pp_params *pp,
+                            uint8_t *d_bits_pool, const int64_t *d_bits_off, int32_t *d_iters,
+                            uint8_t *d_ok, void *d_ws, size_t ws_bytes,
+                            const pc_launch_cfg *cfg, void *stream);
 
 /* Weighted BP: the unrolled decoder with a learnable scale on every check-node
  * output, w[t][s-1][d][row] (iteration t, stage s, d = 0 L sweep / 1 R sweep,

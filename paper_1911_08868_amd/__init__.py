@@ -25,3 +25,4 @@ __all__ = [
 ]
 
 from . import wbp  # noqa: E402  (torch.autograd wrapper of the weighted kernels)
+from . import batched, tune  # noqa: E402,F401

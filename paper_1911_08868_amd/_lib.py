@@ -78,9 +78,9 @@ def lib() -> ctypes.CDLL:
                             ctypes.c_int),
         "pp_mt_bp_decode_ex": ([vp, vp, i64, P(BPParamsC), P(PPParamsC), vp, vp, vp, vp,
                                 P(LaunchCfgC), vp], ctypes.c_int),
-        "polar_batched_workspace_bytes": ([i32], sz),
-        "pp_mt_bp_decode_batched": ([vp, i32, vp, vp, vp, i64, vp, P(BPParamsC), P(PPParamsC),
-                                     vp, vp, vp, vp, vp, sz, vp, vp], ctypes.c_int),
+        "polar_batched_workspace_bytes": ([i64], sz),
+        "pp_mt_bp_decode_batched": ([vp, i32, vp, vp, vp, i64, P(BPParamsC), P(PPParamsC),
+                                     vp, vp, vp, vp, vp, sz, P(LaunchCfgC), vp], ctypes.c_int),
         "wbp_workspace_bytes": ([vp, i64, i32], sz),
         "wbp_forward": ([vp, vp, i64, vp, i32, P(PPParamsC), vp, vp, sz, vp], ctypes.c_int),
         "wbp_backward": ([vp, vp, i64, vp, i32, P(PPParamsC), vp, vp, vp, sz, vp],

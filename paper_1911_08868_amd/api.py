@@ -11,7 +11,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import (BPParamsC, LaunchCfgC, PPParamsC, PP_NONE, STOP_CRC, check, lib)
+from ._lib import (BPParamsC, LaunchCfgC, PPParamsC, PolarError, PP_ALG1, PP_FULL,  # noqa: F401
+                   PP_LASTK, PP_NONE, STOP_CRC, STOP_G, STOP_NONE, check, lib)
 
 
 def _torch():
@@ -173,34 +174,40 @@ def pp_mt_bp_decode(code: Code, llr, bp: BPParams, pp: PPParams, out=None, soft:
     return _decode(code, llr, bp, pp, soft, cfg, out)
 
 
-def batched_workspace_bytes(n_codes: int) -> int:
-    return int(lib().polar_batched_workspace_bytes(n_codes))
+def batched_workspace_bytes(F: int) -> int:
+    return int(lib().polar_batched_workspace_bytes(F))
 
 
-def decode_batched(codes, code_id, llr_off, llr_pool, bp: BPParams, pp: PPParams, bits_pool,
-                   bits_off, iters=None, ok=None, order=None, workspace=None, cfgs=None):
-    """Mixed-length batch through the persistent queue kernel (see the C header)."""
+def decode_batched(codes, code_id, llr_off, llr_pool, bp: BPParams, pp: PPParams | None,
+                   bits_pool, bits_off, iters=None, ok=None, workspace=None,
+                   cfg: LaunchCfg | None = None):
+    """Mixed-length batch through the persistent queue kernel (see the C header).
+
+    Returns the workspace tensor used (allocate it once and pass it back for
+    repeated or graph-captured rounds)."""
     torch = _torch()
     F = code_id.shape[0]
     dev = llr_pool.device
     _need(code_id, torch.int32, (F,), "code_id")
     _need(llr_off, torch.int64, (F,), "llr_off")
     _need(bits_off, torch.int64, (F,), "bits_off")
-    if order is not None:
-        _need(order, torch.int32, (F,), "order")
-    ws_bytes = batched_workspace_bytes(len(codes))
+    if iters is not None:
+        _need(iters, torch.int32, (F,), "iters")
+    if ok is not None:
+        _need(ok, torch.uint8, (F,), "ok")
+    ws_bytes = batched_workspace_bytes(F)
     if workspace is None:
-        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     handles = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
-    cfg_arr = None
-    if cfgs is not None:
-        cfg_arr = (LaunchCfgC * len(cfgs))(*[c.c() for c in cfgs])
-    bpc, ppc = bp.c(), pp.c()
+    bpc = bp.c()
+    ppc = (pp or PPParams()).c()
+    cfgc = cfg.c() if cfg is not None else None
     rc = lib().pp_mt_bp_decode_batched(handles, len(codes), _ptr(code_id), _ptr(llr_off),
-                                       _ptr(llr_pool), F, _ptr(order), ctypes.byref(bpc),
-                                       ctypes.byref(ppc), _ptr(bits_pool), _ptr(bits_off),
-                                       _ptr(iters), _ptr(ok), _ptr(workspace),
-                                       workspace.numel(), cfg_arr, _stream(dev))
+                                       _ptr(llr_pool), F, ctypes.byref(bpc), ctypes.byref(ppc),
+                                       _ptr(bits_pool), _ptr(bits_off), _ptr(iters), _ptr(ok),
+                                       _ptr(workspace), workspace.numel(),
+                                       ctypes.byref(cfgc) if cfgc is not None else None,
+                                       _stream(dev))
     check(rc, "pp_mt_bp_decode_batched")
     return workspace
 

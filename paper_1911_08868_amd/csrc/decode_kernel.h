@@ -57,9 +57,19 @@ constexpr int decode_launch_bound() {
     return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
 }
 
-template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE>
-__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()))
-k_decode(DecodeArgs a) {
+// Iteration parameters shared by every frame source.
+struct DecodeCtl {
+    int32_t max_iter, it_min, stop;
+    float alpha;
+    int32_t T, Q;
+    const int8_t *orders;  // [8][16], in global or kernel-argument memory
+};
+
+// The lock-step slot loop.  Src supplies frames: pop() (slot leader only)
+// returns the next frame or a value >= Src::F when the queue is empty;
+// per frame it gives the LLR pointer, the code tables and the output sinks.
+template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, class Src>
+__device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float *smem, int S) {
     using P = Plan<NLOG, KP, RHO>;
     constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG;
     constexpr int GB = P::GB;
@@ -69,11 +79,10 @@ k_decode(DecodeArgs a) {
     constexpr int LOWBITS = NLOG - KP;
 
     const int tid = threadIdx.x;
-    const int S = blockDim.x / TPS;
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
+    const int64_t F = src.F;
 
-    extern __shared__ __align__(16) float smem[];
     float *const buf = smem + (size_t)slot * 4 * N;  // [L0 | L1 | R0 | R1]
     int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * N);
     uint32_t *const synpart = reinterpret_cast<uint32_t *>(frame_slot + S);
@@ -81,7 +90,7 @@ k_decode(DecodeArgs a) {
     int *const gflag = reinterpret_cast<int *>(gwords + S * 2 * NW);
     int8_t *const ords = reinterpret_cast<int8_t *>(gflag + S);
 
-    if (tid < 8 * 16) ords[tid] = a.orders[tid >> 4][tid & 15];
+    if (tid < 8 * 16) ords[tid] = a.orders[tid];
     if constexpr (GMODE) {
         for (int w = tid; w < S * 2 * NW; w += blockDim.x) gwords[w] = 0u;
     }
@@ -91,7 +100,10 @@ k_decode(DecodeArgs a) {
     int metav[ROWS];
     int baddr[ROWS];
     uint32_t frozen_bits = 0, ubits = 0;
-    int it = 0, q = 0, frame = 0;
+    int it = 0, q = 0;
+    int64_t frame = 0;
+    const uint32_t *tsyn = nullptr;
+    const int32_t *tmeta = nullptr;
     bool active = false, need_new = true;
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
@@ -104,9 +116,9 @@ k_decode(DecodeArgs a) {
         sfor<0, ROWS>([&](auto i) {
             int p = base + GMap<P, G - 1>::off(i);
             int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
-            int m = a.meta[j];
+            int m = tmeta[j];
             metav[i] = m;
-            synv[i] = a.syn[j];
+            synv[i] = tsyn[j];
             frozen_bits |= (m == -2 ? 1u : 0u) << i;
         });
         if constexpr (MAPPED_BOUNDARY) {
@@ -117,20 +129,22 @@ k_decode(DecodeArgs a) {
         }
     };
     auto load_channel = [&](int qq) {
-        const float *src = a.llr + (int64_t)frame * N;
+        const float *lsrc = src.llr(frame);
         const int base = GMap<P, 0>::base(t);
         if constexpr (KP == NLOG) {
             const int8_t *e = ords + qq * 16;
             sfor<0, ROWS>([&](auto i) {
-                st.Lbot[0][i] = src[relabel_to_row(base + GMap<P, 0>::off(i), e, n, 0)];
+                st.Lbot[0][i] = lsrc[relabel_to_row(base + GMap<P, 0>::off(i), e, n, 0)];
             });
         } else {
-            sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[base + GMap<P, 0>::off(i)]; });
+            sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = lsrc[base + GMap<P, 0>::off(i)]; });
         }
     };
     auto start_frame = [&]() {
         it = 0;
         q = 0;
+        tsyn = src.syn(frame);
+        tmeta = src.meta(frame);
         sfor<0, G>([&](auto g) {
             sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
             sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
@@ -151,17 +165,17 @@ k_decode(DecodeArgs a) {
 
     for (;;) {
         // ---- queue: refill finished slots --------------------------------
-        if (need_new && t == 0) frame_slot[slot] = (int)atomicAdd(a.counter, 1u);
+        if (need_new && t == 0) frame_slot[slot] = (int)src.pop();
         __syncthreads();
         if (need_new) {
             frame = frame_slot[slot];
-            active = frame < a.F;
+            active = frame < F;
             need_new = false;
             if (active) start_frame();
         }
         {
             bool any = false;
-            for (int s = 0; s < S; ++s) any |= frame_slot[s] < a.F;
+            for (int s = 0; s < S; ++s) any |= frame_slot[s] < F;
             if (!any) break;
         }
 
@@ -312,23 +326,20 @@ k_decode(DecodeArgs a) {
         // ---- bookkeeping -----------------------------------------------------
         if (active) {
             if (finishing) {
-                const int64_t mo = (int64_t)frame * a.K_msg;
+                uint8_t *mo = src.msg(frame);
                 sfor<0, ROWS>([&](auto i) {
-                    if (metav[i] >= 0) a.msg[mo + metav[i]] = (uint8_t)((ubits >> i) & 1u);
+                    if (metav[i] >= 0) mo[metav[i]] = (uint8_t)((ubits >> i) & 1u);
                 });
-                if (a.soft) {
+                if (src.want_soft()) {
                     const int8_t *e = ords + q * 16;
                     const int base = GMap<P, G - 1>::base(t);
                     sfor<0, ROWS>([&](auto i) {
                         const int p = base + GMap<P, G - 1>::off(i);
                         const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
-                        a.soft[(int64_t)frame * N + j] = st.Ltop[i];
+                        src.soft(frame, j, st.Ltop[i]);
                     });
                 }
-                if (t == 0) {
-                    if (a.iters) a.iters[frame] = it + 1;
-                    if (a.ok) a.ok[frame] = pass ? 1 : 0;
-                }
+                if (t == 0) src.finish(frame, it + 1, pass);
                 need_new = true;
             } else {
                 it += 1;
@@ -344,6 +355,38 @@ k_decode(DecodeArgs a) {
             }
         }
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Frame source of a single-code launch: a queue counter over frames 0..F-1.
+template <int N_>
+struct SingleSrc {
+    const DecodeArgs &a;
+    int64_t F;
+    __device__ SingleSrc(const DecodeArgs &args) : a(args), F(args.F) {}
+    __device__ int64_t pop() { return (int64_t)atomicAdd(a.counter, 1u); }
+    __device__ const float *llr(int64_t f) const { return a.llr + f * N_; }
+    __device__ const uint32_t *syn(int64_t) const { return a.syn; }
+    __device__ const int32_t *meta(int64_t) const { return a.meta; }
+    __device__ uint8_t *msg(int64_t f) const { return a.msg + f * a.K_msg; }
+    __device__ bool want_soft() const { return a.soft != nullptr; }
+    __device__ void soft(int64_t f, int j, float v) const { a.soft[f * N_ + j] = v; }
+    __device__ void finish(int64_t f, int iters, bool pass) const {
+        if (a.iters) a.iters[f] = iters;
+        if (a.ok) a.ok[f] = pass ? 1 : 0;
+    }
+};
+
+template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE>
+__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()))
+k_decode(DecodeArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    constexpr int TPS = Plan<NLOG, KP, RHO>::TPS;
+    const int S = blockDim.x / TPS;
+    DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0]};
+    SingleSrc<(1 << NLOG)> src(a);
+    decode_loop<NLOG, KP, RHO, SCALED, GMODE>(src, c, smem, S);
 }
 
 }  // namespace pbp

@@ -71,13 +71,7 @@ int launch_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_b
 int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
                   hipStream_t stream);
 
-int launch_batched(const pc_code *const *codes, int n_codes, const int32_t *d_code_id,
-                   const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
-                   const int32_t *d_order, const pc_bp_params &bp, int kp_req, int T, int Q,
-                   uint64_t seed, uint8_t *d_bits, const int64_t *d_bits_off, int32_t *d_iters,
-                   uint8_t *d_ok, void *d_ws, size_t ws_bytes, const pc_launch_cfg *cfgs,
-                   hipStream_t stream);
-size_t batched_ws_bytes(int n_codes);
+size_t batched_ws_bytes(int64_t F);
 
 size_t wbp_ws_bytes(const pc_code *code, int64_t F, int T);
 int launch_wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,

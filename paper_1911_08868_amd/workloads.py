@@ -96,11 +96,14 @@ def weighted_bp(torch, pbp, steps=5, warmup=2, F=16384, T=10):
 
 
 def bench_extras(torch, pbp):
-    out = {"weighted_bp": weighted_bp(torch, pbp)}
-    try:
-        from .batched import bench_mixed
-        out["batched_mixed"] = bench_mixed(torch, pbp)
-    except ImportError as e:
-        out["batched_mixed"] = None
-        out["extras_note"] = f"batched decode not available: {e}"
+    from .batched import bench_mixed
+    out = {}
+    for name, fn in (("weighted_bp", weighted_bp), ("batched_mixed", bench_mixed)):
+        try:
+            out[name] = fn(torch, pbp)
+        except Exception as e:  # report the failure in the JSON line, keep the rest
+            out[name] = None
+            out.setdefault("extras_errors", {})[name] = f"{type(e).__name__}: {e}"
+            _log(f"{name} failed: {e}")
+        torch.cuda.empty_cache()
     return out
