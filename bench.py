@@ -49,7 +49,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip side variants")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cfg", type=str, default="",
+                    help="launch shape 'rho,slots' (skips the autotuner)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calib_copy(torch):
+    """A plain device-to-device copy of 2^30 bytes, four times: the reference
+    for scaling FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": 2 ** 30, "copies": 4}), flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -143,6 +159,9 @@ def main():
     import paper_1911_08868_amd as pbp
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        calib_copy(torch)
+        return
     code = pbp.Code(N, K, CRC_W, CRC_POLY, DESIGN_DB)
     F = args.frames
     llrs, msgs = make_inputs(pbp, code, F, torch)
@@ -153,9 +172,13 @@ def main():
     bp = pbp.BPParams(max_iter=MAX_ITER, stop=pbp.STOP_CRC, it_min=IT_MIN)
     pp = pbp.PPParams(mode=pbp.PP_LASTK, k=PP_K, period_T=PP_T, pool_Q=PP_Q, seed=PP_SEED)
     # launch shape from the autotuner, timed on a sample of the 2.0 dB frames
-    cfg, tuned = pbp.tune.tune_decode(torch, code, llrs[2][: min(F, 200_000)], bp, pp,
-                                      path=os.path.join("/tmp", "polarbp_tuned.json"),
-                                      force=True)
+    if args.cfg:
+        rho, slots = (int(v) for v in args.cfg.split(","))
+        cfg, tuned = pbp.LaunchCfg(rho, slots, 0), {"all": "fixed by --cfg"}
+    else:
+        cfg, tuned = pbp.tune.tune_decode(torch, code, llrs[2][: min(F, 200_000)], bp, pp,
+                                          path=os.path.join("/tmp", "polarbp_tuned.json"),
+                                          force=True)
     log(f"tuned launch shape rho={cfg.rho} slots={cfg.slots}: {tuned['all']}")
 
     for w in range(args.warmup):

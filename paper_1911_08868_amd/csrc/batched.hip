@@ -121,7 +121,7 @@ __device__ __forceinline__ void run_bucket(const BatchedArgs &a, float *smem) {
 }
 
 template <int KPQ, int RHO, bool SCALED>
-__global__ void __launch_bounds__(512) k_batched(BatchedArgs a) {
+__global__ void __launch_bounds__(512, (RHO <= 2 ? 4 : 2)) k_batched(BatchedArgs a) {
     extern __shared__ __align__(16) float smem[];
     for (int b = kBuckets - 1; b >= 0; --b) {
         if (a.ctl[b] == 0) continue;

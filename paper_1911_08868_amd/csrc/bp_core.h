@@ -112,9 +112,12 @@ struct GMap {
 // sign(x) sign(y) min(|x|,|y|), optionally scaled.  The sign is the xor of the
 // sign bits; the magnitude min(|x|,|y|) is exact; the only rounding is that
 // of the scale.  Finite inputs and +inf priors never produce NaN.
+// The magnitude uses IEEE-754-2019 minimum (v_minimum3_f32 on gfx950): on the
+// non-negative, non-NaN magnitudes it equals fmin, and unlike fmin it needs no
+// signalling-NaN quieting of its inputs.
 template <bool SCALED>
 __device__ __forceinline__ float cnode(float x, float y, float alpha) {
-    float m = __builtin_fminf(__builtin_fabsf(x), __builtin_fabsf(y));
+    float m = __builtin_elementwise_minimum(__builtin_fabsf(x), __builtin_fabsf(y));
     if constexpr (SCALED) m = alpha * m;
     uint32_t s = (__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u;
     return __uint_as_float(__float_as_uint(m) | s);
@@ -213,10 +216,27 @@ __device__ __forceinline__ int relabel_to_row(int p, const int8_t *e, int n, int
     return j;
 }
 
-// xor-reduce over groups of `width` consecutive lanes (width a power of two
-// <= 64); every lane of the group receives the result
-__device__ __forceinline__ uint32_t xor_reduce(uint32_t v, int width) {
-    for (int m = 1; m < width; m <<= 1) v ^= (uint32_t)__shfl_xor((int)v, m, 64);
+// xor-reduce over groups of W consecutive lanes (W a power of two <= 64,
+// groups aligned to W); every lane of a group receives the result.  Within a
+// 16-lane row the steps are DPP lane swaps (quad_perm, row_half_mirror,
+// row_mirror); across rows the four row totals are read with readlane.
+template <int CTRL>
+__device__ __forceinline__ uint32_t swap_dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t lanes_xor(uint32_t v) {
+    static_assert(W >= 1 && W <= 64 && (W & (W - 1)) == 0, "power-of-two lane group");
+    if constexpr (W >= 2) v ^= swap_dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    if constexpr (W >= 4) v ^= swap_dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (W >= 8) v ^= swap_dpp<0x141>(v);  // row_half_mirror: the other quad of 8
+    if constexpr (W >= 16) v ^= swap_dpp<0x140>(v); // row_mirror: the other half of 16
+    if constexpr (W == 32) v ^= (uint32_t)__shfl_xor((int)v, 16, 64);
+    if constexpr (W == 64) {
+        v = (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) ^ __builtin_amdgcn_readlane((int)v, 16) ^
+                       __builtin_amdgcn_readlane((int)v, 32) ^ __builtin_amdgcn_readlane((int)v, 48));
+    }
     return v;
 }
 

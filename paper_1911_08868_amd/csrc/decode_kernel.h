@@ -56,6 +56,12 @@ template <int NLOG, int RHO>
 constexpr int decode_launch_bound() {
     return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
 }
+// waves per SIMD the register allocation must allow: 4 (<= 128 VGPRs) for
+// two rows per thread, 2 for eight
+template <int RHO>
+constexpr int decode_min_waves() {
+    return RHO <= 2 ? 4 : 2;
+}
 
 // Iteration parameters shared by every frame source.
 struct DecodeCtl {
@@ -97,7 +103,6 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
     Regs<P> st;
     uint32_t synv[ROWS];
-    int metav[ROWS];
     int baddr[ROWS];
     uint32_t frozen_bits = 0, ubits = 0;
     int it = 0, q = 0;
@@ -116,8 +121,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         sfor<0, ROWS>([&](auto i) {
             int p = base + GMap<P, G - 1>::off(i);
             int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
-            int m = tmeta[j];
-            metav[i] = m;
+            const int m = tmeta[j];
             synv[i] = tsyn[j];
             frozen_bits |= (m == -2 ? 1u : 0u) << i;
         });
@@ -215,12 +219,15 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? inf : 0.f; });
             group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
             // hard decision (Sec. II-B): 1 iff L + R < 0; frozen rows stay 0
+            // L + R < 0 with R = +inf (frozen) or 0: negative and not -0 on an
+            // information row; computed without branches from the bit pattern
             uint32_t syn = 0;
             ubits = 0;
             sfor<0, ROWS>([&](auto i) {
-                const bool u = !((frozen_bits >> i) & 1u) && (st.Ltop[i] < 0.f);
-                ubits |= (u ? 1u : 0u) << i;
-                syn ^= u ? synv[i] : 0u;
+                const uint32_t neg = __float_as_uint(st.Ltop[i]) > 0x80000000u ? 1u : 0u;
+                const uint32_t u = neg & ~(frozen_bits >> i) & 1u;
+                ubits |= u << i;
+                syn ^= synv[i] & (0u - u);
             });
             float rb[ROWS];
             group_R<P, G - 1, SCALED>(st, prior, rb, alpha);
@@ -234,7 +241,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 }
             }
             if constexpr (!GMODE) {
-                syn = xor_reduce(syn, TPS < 64 ? TPS : 64);
+                syn = lanes_xor<(TPS < 64 ? TPS : 64)>(syn);
                 if ((t & 63) == 0) synpart[slot * WPS + (t >> 6)] = syn;
             } else {
                 uint32_t *U = gwords + slot * 2 * NW;
@@ -326,19 +333,18 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         // ---- bookkeeping -----------------------------------------------------
         if (active) {
             if (finishing) {
+                // message rows of this thread: original row -> message index
                 uint8_t *mo = src.msg(frame);
+                const int8_t *e = ords + q * 16;
+                const int base = GMap<P, G - 1>::base(t);
+                const bool soft = src.want_soft();
                 sfor<0, ROWS>([&](auto i) {
-                    if (metav[i] >= 0) mo[metav[i]] = (uint8_t)((ubits >> i) & 1u);
+                    const int p = base + GMap<P, G - 1>::off(i);
+                    const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+                    const int m = tmeta[j];
+                    if (m >= 0) mo[m] = (uint8_t)((ubits >> i) & 1u);
+                    if (soft) src.soft(frame, j, st.Ltop[i]);
                 });
-                if (src.want_soft()) {
-                    const int8_t *e = ords + q * 16;
-                    const int base = GMap<P, G - 1>::base(t);
-                    sfor<0, ROWS>([&](auto i) {
-                        const int p = base + GMap<P, G - 1>::off(i);
-                        const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
-                        src.soft(frame, j, st.Ltop[i]);
-                    });
-                }
                 if (t == 0) src.finish(frame, it + 1, pass);
                 need_new = true;
             } else {
@@ -379,7 +385,7 @@ struct SingleSrc {
 };
 
 template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE>
-__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()))
+__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO>()))
 k_decode(DecodeArgs a) {
     extern __shared__ __align__(16) float smem[];
     constexpr int TPS = Plan<NLOG, KP, RHO>::TPS;

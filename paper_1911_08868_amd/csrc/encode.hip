@@ -30,7 +30,7 @@ k_encode(const uint8_t *msg, uint8_t *x, int64_t F, int N, int n, int K, int kms
             if (b && cw) c ^= crc_bit[i];
         }
         if (cw) {
-            c = xor_reduce(c, 64);
+            c = lanes_xor<64>(c);
             if ((tid & 63) == 0) red[tid >> 6] = c;
         }
         __syncthreads();
