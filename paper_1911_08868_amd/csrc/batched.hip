@@ -15,6 +15,7 @@
 //      its slot for the next one.  Longest codes go first so the short, cheap
 //      frames fill the tail.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -192,7 +193,7 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
                             size_t ws_bytes, const pc_launch_cfg *cfg, void *stream) {
     if (!codes || n_codes < 1 || n_codes > kBatchMaxCodes) return fail(PC_EINVAL, "need 1..32 codes");
     if (!bp) return fail(PC_EINVAL, "bp params are NULL");
-    if (F < 0) return fail(PC_EINVAL, "F < 0");
+    if (F < 0 || F > INT32_MAX) return fail(PC_EINVAL, "F must be in [0, 2^31)");
     if (bp->max_iter < 1 || bp->it_min < 1) return fail(PC_EINVAL, "max_iter and it_min must be >= 1");
     if (bp->stop != PC_STOP_CRC && bp->stop != PC_STOP_NONE)
         return fail(PC_ENOTSUP, "batched decoding uses the CRC test (or none)");

@@ -87,7 +87,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     const int tid = threadIdx.x;
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
-    const int64_t F = src.F;
+    const int F = (int)src.F;
 
     float *const buf = smem + (size_t)slot * 4 * N;  // [L0 | L1 | R0 | R1]
     int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * N);
@@ -103,10 +103,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
     Regs<P> st;
     uint32_t synv[ROWS];
+    float prior[ROWS];  // R on level n+1 of this thread's rows: +inf frozen, 0 information
     int baddr[ROWS];
     uint32_t frozen_bits = 0, ubits = 0;
-    int it = 0, q = 0;
-    int64_t frame = 0;
+    int it = 0, q = 0, next_ev = 0;
+    int frame = 0;  // frame indices fit 31 bits (the host checks F)
     const uint32_t *tsyn = nullptr;
     const int32_t *tmeta = nullptr;
     bool active = false, need_new = true;
@@ -124,6 +125,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             const int m = tmeta[j];
             synv[i] = tsyn[j];
             frozen_bits |= (m == -2 ? 1u : 0u) << i;
+            prior[i] = m == -2 ? inf : 0.f;
         });
         if constexpr (MAPPED_BOUNDARY) {
             const int bb = GMap<P, GB>::base(t);
@@ -147,6 +149,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     auto start_frame = [&]() {
         it = 0;
         q = 0;
+        next_ev = a.T;
         tsyn = src.syn(frame);
         tmeta = src.meta(frame);
         sfor<0, G>([&](auto g) {
@@ -215,8 +218,6 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                     sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
                 }
             }
-            float prior[ROWS];
-            sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? inf : 0.f; });
             group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
             // hard decision (Sec. II-B): 1 iff L + R < 0; frozen rows stay 0
             // L + R < 0 with R = +inf (frozen) or 0: negative and not -0 on an
@@ -350,8 +351,10 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             } else {
                 it += 1;
                 if constexpr (KP > 0) {
-                    if (a.Q > 1 && (it % a.T) == 0) {
-                        const int qn = (it / a.T) % a.Q;
+                    // trellis switch at iterations T, 2T, ...: pool entry (it/T) mod Q
+                    if (it == next_ev) {
+                        next_ev += a.T;
+                        const int qn = q + 1 == a.Q ? 0 : q + 1;
                         if (qn != q) {
                             q = qn;
                             apply_event();

@@ -1,6 +1,7 @@
 // host.cpp -- C ABI of the polarbp library: code construction, tables,
 // argument validation and kernel dispatch.  Compiled by hipcc for gfx950.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -293,7 +294,7 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
                          const pc_pp_params *pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok,
                          float *d_soft, const pc_launch_cfg *cfg, void *stream) {
     if (!code) return fail(PC_EINVAL, "code is NULL");
-    if (F < 0) return fail(PC_EINVAL, "F < 0");
+    if (F < 0 || F > INT32_MAX) return fail(PC_EINVAL, "F must be in [0, 2^31)");
     int rc = check_bp(code, bp);
     if (rc) return rc;
     if (F == 0) return PC_OK;
