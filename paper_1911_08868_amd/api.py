@@ -217,6 +217,7 @@ def wbp_workspace_bytes(code: Code, F: int, T: int) -> int:
 
 
 def wbp_forward(code: Code, llr, w, pp: PPParams | None, out, workspace):
+    """workspace=None: forward pass alone, no checkpoints (no backward may follow)."""
     torch = _torch()
     F = llr.shape[0]
     T = w.shape[0]
@@ -226,7 +227,8 @@ def wbp_forward(code: Code, llr, w, pp: PPParams | None, out, workspace):
     ppc = pp.c() if pp is not None else None
     rc = lib().wbp_forward(code.handle, _ptr(llr), F, _ptr(w), T,
                            ctypes.byref(ppc) if ppc is not None else None, _ptr(out),
-                           _ptr(workspace), workspace.numel() * workspace.element_size(),
+                           _ptr(workspace) if workspace is not None else None,
+                           workspace.numel() * workspace.element_size() if workspace is not None else 0,
                            _stream(llr.device))
     check(rc, "wbp_forward")
     return out

@@ -28,22 +28,56 @@ int launch_wbp_n(int n, const WbpLaunch &L) {
     }
 }
 
-// grad_w[i] = sum over workgroups g (in order) of partial[g][i]
-__global__ void __launch_bounds__(256) k_grad_reduce(const float *partial, int64_t groups, int64_t len,
-                                                     float *grad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    float s = 0.f;
-    for (int64_t g = 0; g < groups; ++g) s += partial[g * len + i];
-    grad[i] = s;
+// Deterministic two-level sum of the per-workgroup weight-gradient partials
+// (rows of len floats): the first level sums chunks of kGradChunk consecutive
+// rows, in row order, four columns per thread; the second sums the chunk
+// totals in chunk order.  With one chunk the first level writes the result.
+constexpr int64_t kGradChunk = 64;
+
+__global__ void __launch_bounds__(256) k_grad_chunk_sum(const float4 *partial, int64_t groups, int64_t len4,
+                                                        float4 *out) {
+    const int64_t nchunks = (groups + kGradChunk - 1) / kGradChunk;
+    for (int64_t c = blockIdx.y; c < nchunks; c += gridDim.y) {
+        const int64_t g0 = c * kGradChunk;
+        const int64_t g1 = g0 + kGradChunk < groups ? g0 + kGradChunk : groups;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len4; i += (int64_t)gridDim.x * blockDim.x) {
+            float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+            for (int64_t g = g0; g < g1; ++g) {
+                const float4 v = partial[g * len4 + i];
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+                s.w += v.w;
+            }
+            out[c * len4 + i] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_grad_reduce(const float *mid, int64_t nchunks, int64_t len, float *grad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int64_t c = 0; c < nchunks; ++c) s += mid[c * len + i];
+        grad[i] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_grad_zero(float *grad, int64_t len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        grad[i] = 0.f;
+}
+
+static unsigned clamp_grid(int64_t blocks) {
+    return (unsigned)(blocks < 1 ? 1 : (blocks > 65535 ? 65535 : blocks));
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WbpLayout {
-    size_t ckpt_bytes = 0, partial_bytes = 0, total = 0;
+    size_t ckpt_bytes = 0, partial_bytes = 0, mid_bytes = 0, total = 0;
     int slots = 0;
-    int64_t groups = 0;
+    int64_t groups = 0, nchunks = 0;
 };
 
 static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
@@ -51,8 +85,11 @@ static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
     w.slots = wbp_slots(c->n);
     w.groups = (F + w.slots - 1) / w.slots;
     w.ckpt_bytes = align256((size_t)F * (size_t)(T > 1 ? T - 1 : 0) * (size_t)(c->n - 1) * c->N * sizeof(float));
-    w.partial_bytes = align256((size_t)w.groups * T * c->n * 2 * (size_t)c->N * sizeof(float));
-    w.total = w.ckpt_bytes + w.partial_bytes;
+    const size_t len = (size_t)T * c->n * 2 * (size_t)c->N;
+    w.partial_bytes = align256((size_t)w.groups * len * sizeof(float));
+    w.nchunks = (w.groups + kGradChunk - 1) / kGradChunk;
+    w.mid_bytes = w.nchunks > 1 ? align256((size_t)w.nchunks * len * sizeof(float)) : 0;
+    w.total = w.ckpt_bytes + w.partial_bytes + w.mid_bytes;
     return w;
 }
 
@@ -60,14 +97,15 @@ size_t wbp_ws_bytes(const pc_code *c, int64_t F, int T) { return wbp_layout(c, F
 
 static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const float *d_w, int T,
                       const pc_pp_params *pp, void *d_ws, size_t ws_bytes, WbpLaunch &L,
-                      WbpLayout &lay) {
+                      WbpLayout &lay, bool need_ws = true) {
     if (!c) return fail(PC_EINVAL, "code is NULL");
     if (c->n < 4 || c->n > 10) return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 1024");
     if (T < 1) return fail(PC_EINVAL, "T_unroll must be >= 1");
     if (F < 0) return fail(PC_EINVAL, "F < 0");
     if (F > 0 && (!d_llr || !d_w)) return fail(PC_EINVAL, "null buffer");
     lay = wbp_layout(c, F, T);
-    if (F > 0 && (!d_ws || ws_bytes < lay.total)) return fail(PC_ENOMEM, "workspace too small");
+    const bool no_ws = !need_ws && !d_ws && ws_bytes == 0;
+    if (F > 0 && !no_ws && (!d_ws || ws_bytes < lay.total)) return fail(PC_ENOMEM, "workspace too small");
     std::memset(&L.args, 0, sizeof(L.args));
     int8_t orders[kMaxPool * kMaxLog] = {0};
     int kp = 0, Q = 1, Tev = 1;
@@ -90,8 +128,8 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
     a.F = F;
     a.w = d_w;
     a.T = T;
-    a.ckpt = static_cast<float *>(d_ws);
-    a.partial = reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes);
+    a.ckpt = no_ws ? nullptr : static_cast<float *>(d_ws);
+    a.partial = no_ws ? nullptr : reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes);
     a.meta = c->d.meta;
     a.Tev = Tev;
     a.Q = Q;
@@ -119,7 +157,7 @@ int wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float 
                 size_t ws_bytes, void *stream) {
     WbpLaunch L;
     WbpLayout lay;
-    int rc = wbp_common(code, d_llr, F, d_w, T_unroll, pp, d_ws, ws_bytes, L, lay);
+    int rc = wbp_common(code, d_llr, F, d_w, T_unroll, pp, d_ws, ws_bytes, L, lay, false);
     if (rc) return rc;
     if (F == 0) return PC_OK;
     if (!d_out_llr) return fail(PC_EINVAL, "null output");
@@ -140,7 +178,9 @@ int wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const int64_t len = (int64_t)T_unroll * code->n * 2 * code->N;
     if (F == 0) {
-        hipError_t e = hipMemsetAsync(d_grad_w, 0, (size_t)len * sizeof(float), hs);
+        // a kernel, not a memset, so that the call can be captured in a graph
+        hipLaunchKernelGGL(k_grad_zero, dim3(clamp_grid((len + 255) / 256)), dim3(256), 0, hs, d_grad_w, len);
+        hipError_t e = hipGetLastError();
         return e == hipSuccess ? PC_OK : hip_fail(e, "gradient clear");
     }
     if (!d_grad_out) return fail(PC_EINVAL, "null output adjoint");
@@ -149,8 +189,16 @@ int wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float
     L.stream = hs;
     rc = launch_wbp_n(code->n, L);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, hs,
-                       L.args.partial, lay.groups, len, d_grad_w);
+    const int64_t len4 = len / 4;  // len = T n 2 N, N >= 16
+    float *mid = lay.nchunks > 1
+                     ? reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes + lay.partial_bytes)
+                     : d_grad_w;
+    hipLaunchKernelGGL(k_grad_chunk_sum, dim3(clamp_grid((len4 + 255) / 256), clamp_grid(lay.nchunks)), dim3(256),
+                       0, hs, reinterpret_cast<const float4 *>(L.args.partial), lay.groups, len4,
+                       reinterpret_cast<float4 *>(mid));
+    if (lay.nchunks > 1)
+        hipLaunchKernelGGL(k_grad_reduce, dim3(clamp_grid((len + 255) / 256)), dim3(256), 0, hs, mid, lay.nchunks,
+                           len, d_grad_w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
     return PC_OK;

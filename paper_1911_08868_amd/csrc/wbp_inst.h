@@ -24,7 +24,7 @@ template <int NLOG, int KP>
 int run_wbp(const WbpLaunch &L) {
     using P = Plan<NLOG, KP, 2>;
     const int S = L.slots;
-    const size_t lds = WbpLds<P>::bytes(S);
+    const size_t lds = L.backward ? WbpLds<P, true>::bytes(S) : WbpLds<P, false>::bytes(S);
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for weighted BP");
     if (L.backward)
         hipLaunchKernelGGL((k_wbp_bwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);

@@ -21,10 +21,11 @@
 // of the two boundary messages cross groups through LDS like the messages.
 // Min-sum derivative: for g = sgn(x) sgn(y) min(|x|,|y|), if |x| <= |y| then
 // dg/dx = sgn(y), else dg/dy = sgn(x) (ties route to the first argument).
-// Weight gradients of each iteration are staged per frame in LDS, summed over
-// the workgroup's frames in slot order and written as one partial per
-// workgroup; a second kernel sums the partials in workgroup order, so the
-// result does not depend on scheduling.
+// Each reverse step stages the weight gradients of its group per frame in LDS;
+// the next step (after the barrier that ends this one) sums them over the
+// workgroup's frames in slot order and writes them as this workgroup's
+// partial.  A two-level reduction then sums the partials in workgroup order,
+// so the result does not depend on scheduling.
 #pragma once
 
 #include "bp_core.h"
@@ -50,11 +51,14 @@ struct WbpArgs {
 __device__ __forceinline__ float ms0(float x, float y) { return cnode<false>(x, y, 1.f); }
 __device__ __forceinline__ float sgnf(float v) { return (__float_as_uint(v) >> 31) ? -1.f : 1.f; }
 
-template <class P>
+// LDS per slot.  Forward: the L and R boundary ping-pong pairs (4N floats).
+// Adjoint: the same two pairs, reused by the reverse sweeps for the adjoint
+// handoffs (every phase ends at a barrier), plus a ping-pong pair of
+// weight-gradient staging buffers of RHO N floats each, one per reverse step.
+// The pool orders follow the slots.
+template <class P, bool BWD>
 struct WbpLds {
-    // per slot: L/R ping-pong (4N), adjoint handoffs gR/gL (4N), staged weight
-    // gradients (2 n N); then the pool orders
-    static constexpr size_t per_slot = (size_t)(8 + 2 * P::n) * P::N * sizeof(float);
+    static constexpr size_t per_slot = (size_t)(BWD ? 4 + 2 * P::rho : 4) * P::N * sizeof(float);
     static constexpr size_t bytes(int S) { return (size_t)S * per_slot + 8 * 16; }
 };
 
@@ -149,7 +153,7 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
 // iteration, of the R messages it produces on its interior levels.  Adds the
 // adjoints of the L messages it read into glint/glbot, returns in gtop the
 // adjoint of the R message it read on its top level, and stages the weight
-// gradients (sweep 1) in gw.
+// gradients of its stages (sweep 1) in gw[stage - lo][row].
 template <class P, int g>
 __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
@@ -177,8 +181,8 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 const float a = l2 + r2;
                 const float g1 = ms0(r1, a), g2 = ms0(r1, l1);
-                gw[((lo + sl) * 2 + 1) * N + rowbase + GMap<P, g>::off(i)] = go[i] * g1;
-                gw[((lo + sl) * 2 + 1) * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * g2;
+                gw[sl * N + rowbase + GMap<P, g>::off(i)] = go[i] * g1;
+                gw[sl * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * g2;
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
                 if (__builtin_fabsf(r1) <= __builtin_fabsf(a)) {
@@ -204,7 +208,7 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
 // it produced on its top level; glint: adjoints (already holding the R-sweep
 // contributions) of its interior L messages.  Adds to glbot, adds the
 // adjoints of the entering R state it read into gsint/gstop, stages the
-// weight gradients (sweep 0).
+// weight gradients of its stages (sweep 0) in gw[stage - lo][row].
 template <class P, int g, bool TOPPRIOR>
 __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
@@ -230,8 +234,8 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 const float a = l2 + r2;
                 const float f1 = ms0(l1, a), f2 = ms0(r1, l1);
-                gw[((lo + sl) * 2 + 0) * N + rowbase + GMap<P, g>::off(i)] = go[i] * f1;
-                gw[((lo + sl) * 2 + 0) * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * f2;
+                gw[sl * N + rowbase + GMap<P, g>::off(i)] = go[i] * f1;
+                gw[sl * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * f2;
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
                 if (__builtin_fabsf(l1) <= __builtin_fabsf(a)) {
@@ -265,15 +269,15 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
     const int64_t frame = (int64_t)blockIdx.x * S + slot;
     const bool active = frame < a.F;
     extern __shared__ __align__(16) float smem[];
-    float *const buf = smem + (size_t)slot * (WbpLds<P>::per_slot / sizeof(float));
-    int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * (WbpLds<P>::per_slot / sizeof(float)));
+    float *const buf = smem + (size_t)slot * (WbpLds<P, false>::per_slot / sizeof(float));
+    int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * (WbpLds<P, false>::per_slot / sizeof(float)));
     if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
     __syncthreads();
 
     Regs<P> st;
     int baddr[ROWS], toprow[ROWS];
     uint32_t frozen_bits = 0;
-    int q = 0;
+    int q = 0, next_ev = a.Tev;
     auto maps = [&](int qq) {
         const int8_t *e = ords + qq * 16;
         const int base = GMap<P, G - 1>::base(t);
@@ -304,9 +308,9 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
 
     for (int it = 0; it < a.T; ++it) {
         if constexpr (KP > 0) {
-            const int qn = a.Q > 1 ? (it / a.Tev) % a.Q : 0;
-            if (qn != q) {
-                q = qn;
+            if (it == next_ev) {  // trellis event: the next order of the pool
+                next_ev += a.Tev;
+                q = q + 1 == a.Q ? 0 : q + 1;
                 sfor<GB, G>([&](auto g) {
                     sfor<0, P::RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { st.Rint[g][l][i] = 0.f; }); });
                     if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = 0.f; });
@@ -314,7 +318,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                 if (active) maps(q);
             }
         }
-        if (it > 0 && active) {
+        if (it > 0 && active && a.ckpt) {
             float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS + t;
             RState<P>::each(st, [&](float &v, int k) { ck[(int64_t)k * TPS] = v; });
         }
@@ -392,12 +396,14 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     constexpr int NREG = RState<P>::NREG;
     constexpr int RI = P::RI;
     const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
-    const int64_t frame = (int64_t)blockIdx.x * S + slot;
+    const int64_t frame0 = (int64_t)blockIdx.x * S, frame = frame0 + slot;
     const bool active = frame < a.F;
-    constexpr size_t PS = WbpLds<P>::per_slot / sizeof(float);
+    constexpr size_t PS = WbpLds<P, true>::per_slot / sizeof(float);
     extern __shared__ __align__(16) float smem[];
-    float *const buf = smem + (size_t)slot * PS;     // L0 L1 R0 R1 gR0 gR1 gL0 gL1 | gw[n][2][N]
-    float *const gw = buf + 8 * N;
+    // [A0 A1 | B0 B1 | W0 W1]: L and R boundary pairs of the recomputed
+    // sweeps; the reverse R sweep passes adjoints through A, the reverse L
+    // sweep through B; W holds the weight gradients of one reverse step
+    float *const buf = smem + (size_t)slot * PS;
     int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * PS);
     if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
     __syncthreads();
@@ -413,6 +419,20 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
         sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
     });
     auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
+    // Sum the weight gradients that one reverse step (group g, sweep d)
+    // staged in W[par] over the workgroup's frames, in slot order, and store
+    // them as this workgroup's partial of iteration it.
+    auto flush = [&](auto gc, int d, int par, int it) {
+        constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
+        float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N + lo * 2 * N;
+        const float *w0 = smem + 4 * N + par * RHO * N;
+        for (int idx = tid; idx < r * N; idx += blockDim.x) {
+            float v = 0.f;
+            for (int s = 0; s < S; ++s)
+                if (frame0 + s < a.F) v += w0[(size_t)s * PS + idx];
+            part[((idx / N) * 2 + d) * N + (idx & (N - 1))] = v;
+        }
+    };
 
     for (int it = a.T - 1; it >= 0; --it) {
         const int q = order_at(it);
@@ -519,21 +539,22 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
             });
             // ---- reverse of the R sweep: groups bottom to top ----
             sfor<0, G>([&](auto g) {
+                if constexpr (g > 0) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
                 if (active) {
                     const int base = GMap<P, g>::base(t);
                     float gb[ROWS];
                     if constexpr (g == 0) {
                         sfor<0, ROWS>([&](auto i) { gb[i] = 0.f; });
                     } else {
-                        const float *src = buf + 4 * N + (g & 1) * N;
+                        const float *src = buf + (g & 1) * N;
                         if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { gb[i] = src[baddr[i]]; });
                         else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
                     }
                     float gtop[ROWS];
                     rev_group_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                      wt + base, gw, base);
+                                      wt + base, buf + 4 * N + (g & 1) * RHO * N, base);
                     if constexpr (g < G - 1) {
-                        float *dst = buf + 4 * N + ((g + 1) & 1) * N;
+                        float *dst = buf + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
                     }
                 }
@@ -546,8 +567,15 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
             sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
         });
         // ---- reverse of the L sweep: groups top to bottom ----
+        const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
         sfor<0, G>([&](auto k) {
             constexpr int g = G - 1 - k;
+            if constexpr (k == 0) {
+                if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
+            } else {
+                flush(std::integral_constant<int, g + 1>{}, 0, (step0 + k - 1) & 1, it);
+            }
+            float *const gws = buf + 4 * N + ((step0 + k) & 1) * RHO * N;
             if (active) {
                 const int base = GMap<P, g>::base(t);
                 float gt[ROWS];
@@ -555,33 +583,26 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                     if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
                     else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
                     rev_group_L<P, g, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g], gsi[g],
-                                            gst[g], wt + base, gw, base);
+                                            gst[g], wt + base, gws, base);
                 } else {
-                    const float *src = buf + 6 * N + ((g + 1) & 1) * N;
+                    const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
                     rev_group_L<P, g, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g], glb[g],
-                                             gsi[g], gst[g], wt + base, gw, base);
+                                             gsi[g], gst[g], wt + base, gws, base);
                 }
                 if constexpr (g > 0) {
-                    float *dst = buf + 6 * N + (g & 1) * N;
+                    float *dst = buf + 2 * N + (g & 1) * N;
                     if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { dst[baddr[i]] = glb[g][i]; });
                     else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[g][i]; });
                 }
             }
             __syncthreads();
         });
-        // ---- weight gradients of iteration it: sum over this workgroup's frames
-        {
+        flush(std::integral_constant<int, 0>{}, 0, (step0 + G - 1) & 1, it);
+        if (lastit) {
+            // the last iteration runs no R sweep: its R weights get no gradient
             float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
-            for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
-                float v = 0.f;
-                const bool rsweep = ((idx / N) & 1) != 0;
-                if (!(lastit && rsweep)) {
-                    for (int s = 0; s < S; ++s)
-                        if ((int64_t)blockIdx.x * S + s < a.F) v += smem[(size_t)s * PS + 8 * N + idx];
-                }
-                part[idx] = v;
-            }
+            for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
         }
         __syncthreads();
     }

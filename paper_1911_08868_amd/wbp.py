@@ -1,11 +1,13 @@
 """Weighted BP as a differentiable torch operation.
 
-``WeightedBP.apply(llr, w, ctx_obj)`` runs ``wbp_forward`` (which checkpoints
-the per-iteration R messages in a device workspace) and, on backward,
-``wbp_backward`` (the hand-written adjoint kernel) for the weight gradient.
-The channel LLRs are treated as data (no gradient).  ``WeightedBPDecoder``
-holds the learnable weights w[T][n][2][N], initialised to 1 (plain min-sum
-BP), and the workspace.
+``WeightedBP.apply(llr, w, state, keep)`` runs ``wbp_forward`` (which checkpoints
+the per-iteration R messages in a device workspace owned by that call's
+autograd context) and, on backward, ``wbp_backward`` (the hand-written adjoint
+kernel) for the weight gradient.  With keep=False (the decoder passes it under
+torch.no_grad() or for frozen weights) the forward pass runs alone, without
+checkpoints.  The channel LLRs are treated as
+data (no gradient).  ``WeightedBPDecoder`` holds the learnable weights
+w[T][n][2][N], initialised to 1 (plain min-sum BP).
 """
 from __future__ import annotations
 
@@ -15,40 +17,40 @@ from . import api
 
 
 class _WbpState:
-    """Code, schedule and a reusable workspace for one decoder."""
+    """Code and schedule of one decoder."""
 
     def __init__(self, code: api.Code, T: int, pp: api.PPParams | None):
         self.code, self.T, self.pp = code, T, pp
-        self.ws = None
-        self.ws_frames = -1
 
     def workspace(self, F: int, device) -> torch.Tensor:
+        # one per forward call (from torch's caching allocator), so that a
+        # second forward before the first backward cannot overwrite the
+        # first call's checkpoints
         need = api.wbp_workspace_bytes(self.code, F, self.T)
-        if self.ws is None or self.ws.numel() < need:
-            self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
-        return self.ws
+        return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
 
 
 class WeightedBP(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, llr, w, state: _WbpState):
+    def forward(ctx, llr, w, state: _WbpState, keep: bool = True):
         F = llr.shape[0]
         out = torch.empty((F, state.code.N), dtype=torch.float32, device=llr.device)
-        ws = state.workspace(F, llr.device)
+        ws = state.workspace(F, llr.device) if keep else None
         api.wbp_forward(state.code, llr, w.detach(), state.pp, out, ws)
         ctx.save_for_backward(llr, w)
         ctx.state = state
+        ctx.ws = ws
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
         llr, w = ctx.saved_tensors
         state = ctx.state
+        if ctx.ws is None:
+            raise RuntimeError("weighted BP forward ran without checkpoints (keep=False): no backward")
         gw = torch.empty_like(w)
-        # the checkpoints of the forward call are still in the workspace
-        api.wbp_backward(state.code, llr, w.detach(), state.pp, grad_out.contiguous(), gw,
-                         state.ws)
-        return None, gw, None
+        api.wbp_backward(state.code, llr, w.detach(), state.pp, grad_out.contiguous(), gw, ctx.ws)
+        return None, gw, None, None
 
 
 class WeightedBPDecoder(torch.nn.Module):
@@ -62,7 +64,8 @@ class WeightedBPDecoder(torch.nn.Module):
         self._state = _WbpState(code, T, pp)
 
     def forward(self, llr):
-        return WeightedBP.apply(llr, self.weight, self._state)
+        keep = torch.is_grad_enabled() and self.weight.requires_grad
+        return WeightedBP.apply(llr, self.weight, self._state, keep)
 
 
 def bce_on_information_bits(out_llr, u_info_bits, info_idx):

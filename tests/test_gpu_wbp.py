@@ -118,3 +118,71 @@ def test_autograd_training_step(orc, pbp):
                               o.grad.numpy())
     np.testing.assert_allclose(g, ref, rtol=0, atol=_grad_tol(ref))
     assert abs(loss.item() - l2.item()) < 1e-5 * max(1.0, abs(l2.item()))
+
+
+@pytest.mark.parametrize("N,K,T,F", [(64, 32, 3, 16 * 70 + 5), (16, 8, 2, 64 * 65 + 3)])
+def test_weighted_gradient_over_many_workgroups(orc, pbp, N, K, T, F):
+    # more than 64 workgroup partials: both levels of the gradient reduction
+    n = N.bit_length() - 1
+    oc, u, llr = _setup(orc, N, K, F, seed=3 + F)
+    rng = np.random.default_rng(F)
+    w = rng.uniform(0.7, 1.3, (T, n, 2, N)).astype(np.float32).astype(np.float64)
+    gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
+    out, gw = _gpu(pbp, oc, llr, w, T, None, gout)
+    opp = orc.WbpParams(fp32=True)
+    assert np.array_equal(out.view(np.uint32), orc.wbp_forward(oc, llr, w, opp).astype(np.float32).view(np.uint32))
+    ref_gw, _ = orc.wbp_backward(oc, llr, w, opp, gout)
+    np.testing.assert_allclose(gw, ref_gw, rtol=0, atol=_grad_tol(ref_gw))
+
+
+def test_weighted_empty_batch_gives_zero_gradient(pbp):
+    import torch
+    code = pbp.Code(64, 32, 0, 0, 2.5)
+    w = torch.ones((3, 6, 2, 64), dtype=torch.float32, device="cuda")
+    gw = torch.full_like(w, 5.0)
+    llr = torch.empty((0, 64), dtype=torch.float32, device="cuda")
+    ws = torch.empty(1, dtype=torch.uint8, device="cuda")
+    pbp.wbp_backward(code, llr, w, None, torch.empty((0, 64), dtype=torch.float32, device="cuda"), gw, ws)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(gw).item() == 0
+
+
+def test_weighted_forward_without_checkpoints(orc, pbp):
+    import torch
+    oc, u, llr = _setup(orc, 256, 144, 70, seed=21)
+    code = pbp.Code(256, 144, 0, 0, 2.5)
+    rng = np.random.default_rng(2)
+    w = torch.from_numpy(rng.uniform(0.8, 1.2, (5, 8, 2, 256)).astype(np.float32)).cuda()
+    x = torch.from_numpy(llr).cuda()
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=3, period_T=2, pool_Q=4, seed=3)
+    a = torch.empty((70, 256), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ws = torch.empty(pbp.wbp_workspace_bytes(code, 70, 5), dtype=torch.uint8, device="cuda")
+    pbp.wbp_forward(code, x, w, pp, a, ws)
+    pbp.wbp_forward(code, x, w, pp, b, None)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    dec = pbp.wbp.WeightedBPDecoder(code, 5)
+    with torch.no_grad():
+        o = dec(x)
+    ref = orc.wbp_forward(oc, llr, np.ones((5, 8, 2, 256)), orc.WbpParams(fp32=True))
+    assert np.array_equal(o.cpu().numpy().view(np.uint32), ref.astype(np.float32).view(np.uint32))
+
+
+def test_two_forwards_before_backward(orc, pbp):
+    # each forward call keeps its own checkpoints
+    import torch
+    oc, u, llr1 = _setup(orc, 64, 32, 40, seed=31)
+    _, _, llr2 = _setup(orc, 64, 32, 40, seed=32)
+    code = pbp.Code(64, 32, 0, 0, 2.5)
+    dec = pbp.wbp.WeightedBPDecoder(code, 3)
+    g = torch.from_numpy(np.random.default_rng(4).normal(size=(40, 64)).astype(np.float32)).cuda()
+    o1 = dec(torch.from_numpy(llr1).cuda())
+    o2 = dec(torch.from_numpy(llr2).cuda())
+    (o1 * g).sum().backward()
+    g1 = dec.weight.grad.clone()
+    dec.weight.grad = None
+    (o2 * g).sum().backward()
+    ref1, _ = orc.wbp_backward(oc, llr1, np.ones((3, 6, 2, 64)), orc.WbpParams(fp32=True),
+                               g.cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(g1.cpu().numpy(), ref1, rtol=0, atol=_grad_tol(ref1))
