@@ -95,12 +95,13 @@ def make_inputs(pbp, code, frames, torch, seed=2024):
 
 def alg_ops(iters):
     """Algorithmic VALU lane-ops of a decode launch: every processing element
-    (n N/2 per sweep) costs 2 min-sum evaluations (min of magnitudes, sign xor,
-    sign apply) and 2 additions, 8 ops, so a sweep costs 4 n N.  A frame needs
-    `iters` L sweeps and iters - 1 R sweeps (the R sweep after the deciding L
-    sweep cannot change the output)."""
+    (n N/2 per sweep) costs 2 additions and 2 check-function evaluations of 2
+    instructions each on gfx950 (clamp of one input by the magnitude of the
+    other, then the other's sign applied), 6 ops, so a sweep costs 3 n N.  A
+    frame needs `iters` L sweeps and iters - 1 R sweeps (the R sweep after the
+    deciding L sweep cannot change the output)."""
     n = 10
-    per_sweep = 4 * n * N
+    per_sweep = 3 * n * N
     return per_sweep * (2.0 * iters.double().sum().item() - iters.numel())
 
 
@@ -219,12 +220,15 @@ def main():
         ops_total += ops
     achieved = ops_total / (launch_ms / 1e3) / 1e12
     it_total = sum(o[1].double().sum().item() for o in outs)
-    lds_bytes_per_it = 16 * 4 * N  # 4 group boundaries x (L,R written and read) x N x 4 B
+    # group boundaries: the unpermuted 6 stages and the permuted 4 are each cut
+    # into groups of at most rho stages
+    boundaries = -(-(10 - PP_K) // cfg.rho) + -(-PP_K // cfg.rho) - 1
+    lds_bytes_per_it = boundaries * 4 * 4 * N  # (L, R) x (written, read) x N x 4 B per boundary
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
             "kernel": f"k_decode<n=10,k=4,rho={cfg.rho}>", "launch": {"rho": cfg.rho, "slots": cfg.slots,
                                                                    "tuned_ms": tuned["all"]},
-            "ops_per_frame_iteration": 8 * 10 * N,
+            "ops_per_frame_iteration": 6 * 10 * N,
             "launch_ms_avg": round(launch_ms / len(SNRS), 3),
             "lds": {"bytes_per_frame_iteration": lds_bytes_per_it,
                     "achieved_TBs": round(lds_bytes_per_it * it_total / (launch_ms / 1e3) / 1e12, 3),

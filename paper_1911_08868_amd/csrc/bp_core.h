@@ -123,6 +123,23 @@ __device__ __forceinline__ float cnode(float x, float y, float alpha) {
     return __uint_as_float(__float_as_uint(m) | s);
 }
 
+// The same check function in clamp form, two instructions on gfx950: y
+// clamped to [-|x|, |x|] (v_med3_f32 with abs/neg source modifiers) has the
+// sign of y and the magnitude min(|x|,|y|); flipping its sign bit by that of
+// x (v_bitop3_b32) gives sign(x) sign(y) min(|x|,|y|).  Every nonzero result
+// equals cnode's bit for bit; a zero result (both inputs zero) may carry the
+// other sign.  A zero's sign reaches no nonzero message (it only meets the
+// check function, whose zero stays zero, and additions, where a nonzero
+// addend wins) and no decision (-0 and +0 both decide 0), so decoding is
+// unchanged.  The bound x should be the operand less likely to be zero.
+template <bool SCALED>
+__device__ __forceinline__ float cnode_clamp(float x, float y, float alpha) {
+    const float ax = __builtin_fabsf(x);
+    float t = __builtin_amdgcn_fmed3f(y, ax, -ax);
+    if constexpr (SCALED) t = alpha * t;
+    return __uint_as_float(__float_as_uint(t) ^ (__float_as_uint(x) & 0x80000000u));
+}
+
 // ---------------------------------------------------------------------------
 // Register state of one thread for one frame.
 template <class P>
@@ -159,8 +176,8 @@ __device__ __forceinline__ void group_L(Regs<P> &S, const float (&rtop)[P::ROWS]
                     r2 = rtop[ip];
                 }
                 const float l1 = cur[i], l2 = cur[ip];
-                nxt[i] = cnode<SCALED>(l1, l2 + r2, alpha);
-                nxt[ip] = cnode<SCALED>(r1, l1, alpha) + l2;
+                nxt[i] = cnode_clamp<SCALED>(l1, l2 + r2, alpha);
+                nxt[ip] = cnode_clamp<SCALED>(l1, r1, alpha) + l2;
             }
         });
         if constexpr (sl + 1 < r) {
@@ -196,8 +213,8 @@ __device__ __forceinline__ void group_R(Regs<P> &S, const float (&rtop)[P::ROWS]
                     l2 = S.Lbot[g][ip];
                 }
                 const float r1 = cur[i], r2 = cur[ip];
-                nxt[i] = cnode<SCALED>(r1, l2 + r2, alpha);
-                nxt[ip] = cnode<SCALED>(r1, l1, alpha) + r2;
+                nxt[i] = cnode_clamp<SCALED>(l2 + r2, r1, alpha);
+                nxt[ip] = cnode_clamp<SCALED>(l1, r1, alpha) + r2;
             }
         });
         if constexpr (sl > 0) {
@@ -206,6 +223,14 @@ __device__ __forceinline__ void group_R(Regs<P> &S, const float (&rtop)[P::ROWS]
         sfor<0, P::ROWS>([&](auto i) { cur[i] = nxt[i]; });
     });
     sfor<0, P::ROWS>([&](auto i) { out[i] = cur[i]; });
+}
+
+// float at a byte offset from p (precomputed byte offsets save the scaling)
+__device__ __forceinline__ float &byte_at(float *p, int byte_off) {
+    return *reinterpret_cast<float *>(reinterpret_cast<char *>(p) + byte_off);
+}
+__device__ __forceinline__ float byte_at(const float *p, int byte_off) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + byte_off);
 }
 
 // relabelled row p -> original row for stage order e[0..n-1]: bit s of p is

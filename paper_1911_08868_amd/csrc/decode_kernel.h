@@ -96,7 +96,8 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     int *const gflag = reinterpret_cast<int *>(gwords + S * 2 * NW);
     int8_t *const ords = reinterpret_cast<int8_t *>(gflag + S);
 
-    if (tid < 8 * 16) ords[tid] = a.orders[tid];
+    // every workgroup size, also below 128 threads, copies the whole pool
+    for (int i = tid; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i];
     if constexpr (GMODE) {
         for (int w = tid; w < S * 2 * NW; w += blockDim.x) gwords[w] = 0u;
     }
@@ -104,8 +105,8 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     Regs<P> st;
     uint32_t synv[ROWS];
     float prior[ROWS];  // R on level n+1 of this thread's rows: +inf frozen, 0 information
-    int baddr[ROWS];
-    uint32_t frozen_bits = 0, ubits = 0;
+    int baddr[ROWS];  // byte offsets of the relabelled boundary rows
+    uint32_t ubits = 0;
     int it = 0, q = 0, next_ev = 0;
     int frame = 0;  // frame indices fit 31 bits (the host checks F)
     const uint32_t *tsyn = nullptr;
@@ -114,23 +115,24 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
 
+    // decision of register row i
+    auto decide = [&](auto i) { return st.Ltop[i] < -prior[i]; };
+
     // --- per-frame (re)initialisation helpers ------------------------------
     auto load_top_info = [&](int qq) {
         const int8_t *e = ords + qq * 16;
-        frozen_bits = 0;
         const int base = GMap<P, G - 1>::base(t);
         sfor<0, ROWS>([&](auto i) {
             int p = base + GMap<P, G - 1>::off(i);
             int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
             const int m = tmeta[j];
             synv[i] = tsyn[j];
-            frozen_bits |= (m == -2 ? 1u : 0u) << i;
             prior[i] = m == -2 ? inf : 0.f;
         });
         if constexpr (MAPPED_BOUNDARY) {
             const int bb = GMap<P, GB>::base(t);
             sfor<0, ROWS>([&](auto i) {
-                baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS);
+                baddr[i] = 4 * relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS);
             });
         }
     };
@@ -172,15 +174,20 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
     for (;;) {
         // ---- queue: refill finished slots --------------------------------
-        if (need_new && t == 0) frame_slot[slot] = (int)src.pop();
-        __syncthreads();
+        // one frame per workgroup (S == 1): need_new is uniform, so the queue
+        // round trip and its barrier happen only when the frame ends
+        const bool refill = S > 1 || need_new;
+        if (refill) {
+            if (need_new && t == 0) frame_slot[slot] = (int)src.pop();
+            __syncthreads();
+        }
         if (need_new) {
             frame = frame_slot[slot];
             active = frame < F;
             need_new = false;
             if (active) start_frame();
         }
-        {
+        if (refill) {
             bool any = false;
             for (int s = 0; s < S; ++s) any |= frame_slot[s] < F;
             if (!any) break;
@@ -192,7 +199,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 if constexpr (g > 0) {
                     const float *lb = buf + (g & 1) * N;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
-                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = byte_at(lb, baddr[i]); });
                     } else {
                         const int base = GMap<P, g>::base(t);
                         sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
@@ -212,30 +219,29 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             if constexpr (G > 1) {
                 const float *lb = buf + ((G - 1) & 1) * N;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
-                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = byte_at(lb, baddr[i]); });
                 } else {
                     const int base = GMap<P, G - 1>::base(t);
                     sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
                 }
             }
             group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
-            // hard decision (Sec. II-B): 1 iff L + R < 0; frozen rows stay 0
-            // L + R < 0 with R = +inf (frozen) or 0: negative and not -0 on an
-            // information row; computed without branches from the bit pattern
+            // hard decision (Sec. II-B): u = 1 iff L + R < 0 on level n+1,
+            // R = +inf (frozen) or 0, i.e. iff L < -R (one compare: never for a
+            // frozen row, and -0 decides 0); the CRC syndrome of the decided
+            // rows accumulates their columns
             uint32_t syn = 0;
-            ubits = 0;
-            sfor<0, ROWS>([&](auto i) {
-                const uint32_t neg = __float_as_uint(st.Ltop[i]) > 0x80000000u ? 1u : 0u;
-                const uint32_t u = neg & ~(frozen_bits >> i) & 1u;
-                ubits |= u << i;
-                syn ^= synv[i] & (0u - u);
-            });
+            sfor<0, ROWS>([&](auto i) { syn ^= decide(i) ? synv[i] : 0u; });
+            if constexpr (GMODE) {
+                ubits = 0;
+                sfor<0, ROWS>([&](auto i) { ubits |= (decide(i) ? 1u : 0u) << i; });
+            }
             float rb[ROWS];
             group_R<P, G - 1, SCALED>(st, prior, rb, alpha);
             if constexpr (G > 1) {
                 float *rt = buf + 2 * N + ((G - 1) & 1) * N;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
-                    sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                    sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
                 } else {
                     const int base = GMap<P, G - 1>::base(t);
                     sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
@@ -288,7 +294,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 if constexpr (g > 0) {
                     float *rt = buf + 2 * N + (g & 1) * N;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
-                        sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                        sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
                     } else {
                         sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
                     }
@@ -343,7 +349,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                     const int p = base + GMap<P, G - 1>::off(i);
                     const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
                     const int m = tmeta[j];
-                    if (m >= 0) mo[m] = (uint8_t)((ubits >> i) & 1u);
+                    if (m >= 0) mo[m] = (uint8_t)(decide(i) ? 1 : 0);
                     if (soft) src.soft(frame, j, st.Ltop[i]);
                 });
                 if (t == 0) src.finish(frame, it + 1, pass);

@@ -271,7 +271,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
     extern __shared__ __align__(16) float smem[];
     float *const buf = smem + (size_t)slot * (WbpLds<P, false>::per_slot / sizeof(float));
     int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * (WbpLds<P, false>::per_slot / sizeof(float)));
-    if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
+    for (int i = tid; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i >> 4][i & 15];
     __syncthreads();
 
     Regs<P> st;
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     // sweep through B; W holds the weight gradients of one reverse step
     float *const buf = smem + (size_t)slot * PS;
     int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * PS);
-    if (tid < 128) ords[tid] = a.orders[tid >> 4][tid & 15];
+    for (int i = tid; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i >> 4][i & 15];
     __syncthreads();
 
     Regs<P> st;                         // entering R state and this iteration's L messages

@@ -52,6 +52,16 @@ def decode_candidates(N: int):
     return out
 
 
+def _pick(results, default=(2, 1, 0), margin=0.02):
+    """Fastest shape, but the default unless another beats it by the margin:
+    timing noise must not flip the choice between near-equal shapes."""
+    best = min(results, key=lambda r: r[1])
+    for cfg, ms in results:
+        if cfg == default and best[1] * (1 + margin) >= ms:
+            return (cfg, ms)
+    return best
+
+
 def _time(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -84,7 +94,7 @@ def tune_decode(torch, code: api.Code, llr, bp: api.BPParams, pp: api.PPParams |
         except api.PolarError:
             continue
         results.append(((cfg.rho, cfg.slots, cfg.grid), ms))
-    best = min(results, key=lambda r: r[1])
+    best = _pick(results)
     entry = {"cfg": list(best[0]), "ms": best[1], "all": [[list(c), m] for c, m in results],
              "frames": F}
     cache.setdefault(dk, {})[key] = entry
@@ -114,7 +124,7 @@ def tune_batched(torch, dec, reps: int = 2, path: str = _CACHE, force=False):
             continue
         results.append(((cfg.rho, cfg.slots, cfg.grid), ms))
     dec.cfg = saved
-    best = min(results, key=lambda r: r[1])
+    best = _pick(results)
     entry = {"cfg": list(best[0]), "ms": best[1], "all": [[list(c), m] for c, m in results],
              "frames": dec.F}
     cache.setdefault(dk, {})[key] = entry
