@@ -95,14 +95,15 @@ def make_inputs(pbp, code, frames, torch, seed=2024):
 
 def alg_ops(iters):
     """Algorithmic VALU lane-ops of a decode launch: every processing element
-    (n N/2 per sweep) costs 2 additions and 2 check-function evaluations of 2
+    (N/2 per stage) costs 2 additions and 2 check-function evaluations of 2
     instructions each on gfx950 (clamp of one input by the magnitude of the
-    other, then the other's sign applied), 6 ops, so a sweep costs 3 n N.  A
-    frame needs `iters` L sweeps and iters - 1 R sweeps (the R sweep after the
-    deciding L sweep cannot change the output)."""
+    other, then the other's sign applied), 6 ops, so a stage costs 3 N.  A
+    frame needs `iters` L sweeps of n stages and iters - 1 R sweeps (the R
+    sweep after the deciding L sweep cannot change the output) of n - 1
+    stages (the R messages on the channel level are never read)."""
     n = 10
-    per_sweep = 3 * n * N
-    return per_sweep * (2.0 * iters.double().sum().item() - iters.numel())
+    it = iters.double().sum().item()
+    return 3 * N * (n * it + (n - 1) * (it - iters.numel()))
 
 
 def run_decode_set(pbp, code, llrs, outs, bp, pp, torch, events=None, cfg=None):
@@ -228,7 +229,7 @@ def main():
             "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
             "kernel": f"k_decode<n=10,k=4,rho={cfg.rho}>", "launch": {"rho": cfg.rho, "slots": cfg.slots,
                                                                    "tuned_ms": tuned["all"]},
-            "ops_per_frame_iteration": 6 * 10 * N,
+            "ops_per_frame_iteration": 3 * N * (10 + 9),
             "launch_ms_avg": round(launch_ms / len(SNRS), 3),
             "lds": {"bytes_per_frame_iteration": lds_bytes_per_it,
                     "achieved_TBs": round(lds_bytes_per_it * it_total / (launch_ms / 1e3) / 1e12, 3),

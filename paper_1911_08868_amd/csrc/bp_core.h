@@ -105,7 +105,31 @@ struct GMap {
             return (t & ((1 << lo) - 1)) | ((t >> lo) << (lo + r));
         }
     }
+    // row position of thread-index bit k (k < tbits): the non-stage
+    // positions in increasing order
+    static constexpr int tpos(int k) { return k < lo ? k : k + r; }
 };
+
+// Is the exchange across the boundary between groups g and g+1 local to each
+// wave?  Then no workgroup barrier is needed there: each wave reads only rows
+// its own lanes wrote, and one wave's LDS accesses execute in order.  True
+// when a frame fits in one wave, or when the wave-index bits of the thread
+// index (bits 6.. of t) sit at the same row positions in both groups and, at
+// the relabelled boundary, below the permuted range.
+template <class P, int g>
+constexpr bool wave_local_boundary(bool mapped_at_gb) {
+    if constexpr (P::TPS <= 64) {
+        return true;
+    } else {
+        constexpr int tb = P::n - P::rho;
+        for (int k = 6; k < tb; ++k) {
+            const int a = GMap<P, g>::tpos(k), b = GMap<P, g + 1>::tpos(k);
+            if (a != b) return false;
+            if (mapped_at_gb && g + 1 == P::GB && a >= P::n - P::kp) return false;
+        }
+        return true;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Check function of the processing element (Sec. II-B): min-sum

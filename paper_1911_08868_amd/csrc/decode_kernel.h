@@ -63,6 +63,20 @@ constexpr int decode_min_waves() {
     return RHO <= 2 ? 4 : 2;
 }
 
+// Synchronisation at a group boundary: a workgroup barrier, or, where the
+// exchange stays inside each wave, only a compiler barrier that keeps the
+// LDS stores before the loads.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void boundary_sync() {
+    if constexpr (WAVE_LOCAL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Iteration parameters shared by every frame source.
 struct DecodeCtl {
     int32_t max_iter, it_min, stop;
@@ -211,7 +225,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 const int base = GMap<P, g>::base(t);
                 sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
             }
-            __syncthreads();
+            boundary_sync<wave_local_boundary<P, g>(MAPPED_BOUNDARY)>();
         });
 
         // ---- last group: L pass, decision, R pass ---------------------------
@@ -308,7 +322,15 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                     });
                 }
             }
-            __syncthreads();
+            // the R messages written here are read by group g-1; after the
+            // last step only the G test reads what every thread wrote (the
+            // next LDS writes, at the first L boundary, are ordered behind
+            // the cross-wave barriers of this iteration)
+            if constexpr (g > 0) {
+                boundary_sync<!GMODE && wave_local_boundary<P, g - 1>(MAPPED_BOUNDARY)>();
+            } else if constexpr (GMODE) {
+                __syncthreads();
+            }
         });
 
         if constexpr (GMODE) {
