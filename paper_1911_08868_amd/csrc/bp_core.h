@@ -74,6 +74,20 @@ struct Plan {
     static constexpr int WPS = TPS >= 64 ? TPS / 64 : 1;  // waves per slot
 };
 
+// Padded layout of one boundary buffer in LDS: PAD words after every 2^SH
+// rows break the power-of-two strides with which the thread -> row maps
+// would otherwise hit the same banks (2- to 8-way conflicts).  A thread's
+// base row and a register's offset occupy disjoint bits, so the padded
+// address is a per-thread part plus a compile-time constant.  PAD is a
+// multiple of 4, so the rows a thread owns contiguously stay 16-byte aligned.
+template <class P>
+struct LdsPad {
+    static constexpr int SH = P::rho == 2 ? (P::n >= 8 ? 6 : 5) : (P::n >= 9 ? 6 : 5);
+    static constexpr int PAD = P::n <= 5 ? 0 : (P::rho == 2 ? 12 : (P::n >= 9 ? 8 : 4));
+    static constexpr int words = P::N + PAD * (P::N >> SH);
+    __host__ __device__ static constexpr int at(int row) { return row + PAD * (row >> SH); }
+};
+
 // Thread -> row map of group g.  Register index i: its low r bits are the
 // group's stage bits (positions lo..lo+r-1); the thread index t fills the
 // remaining positions from the lowest up, and the high RHO-r bits of i fill
@@ -108,6 +122,9 @@ struct GMap {
     // row position of thread-index bit k (k < tbits): the non-stage
     // positions in increasing order
     static constexpr int tpos(int k) { return k < lo ? k : k + r; }
+    // the same rows in the padded LDS layout
+    __device__ static __forceinline__ int pbase(int t) { return LdsPad<P>::at(base(t)); }
+    static constexpr int poff(int i) { return LdsPad<P>::at(off(i)); }
 };
 
 // Is the exchange across the boundary between groups g and g+1 local to each

@@ -42,7 +42,7 @@ struct DecodeLds {
     static constexpr int NW = (P::N + 31) / 32;
     // bytes of dynamic LDS for S slots
     static constexpr size_t bytes(int S) {
-        return (size_t)S * 4 * P::N * sizeof(float)   // L/R boundary ping-pong buffers
+        return (size_t)S * 4 * LdsPad<P>::words * sizeof(float)  // L/R boundary ping-pong buffers
                + (size_t)S * sizeof(int)                // frame of each slot
                + (size_t)S * P::WPS * sizeof(uint32_t)  // syndrome partials
                + (size_t)S * 2 * NW * sizeof(uint32_t)  // G test words (u_hat, x_hat)
@@ -103,8 +103,9 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     const int t = tid & (TPS - 1);
     const int F = (int)src.F;
 
-    float *const buf = smem + (size_t)slot * 4 * N;  // [L0 | L1 | R0 | R1]
-    int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * N);
+    constexpr int NP = LdsPad<P>::words;  // padded length of one boundary buffer
+    float *const buf = smem + (size_t)slot * 4 * NP;  // [L0 | L1 | R0 | R1]
+    int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * NP);
     uint32_t *const synpart = reinterpret_cast<uint32_t *>(frame_slot + S);
     uint32_t *const gwords = synpart + S * WPS;
     int *const gflag = reinterpret_cast<int *>(gwords + S * 2 * NW);
@@ -146,7 +147,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         if constexpr (MAPPED_BOUNDARY) {
             const int bb = GMap<P, GB>::base(t);
             sfor<0, ROWS>([&](auto i) {
-                baddr[i] = 4 * relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS);
+                baddr[i] = 4 * LdsPad<P>::at(relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS));
             });
         }
     };
@@ -211,19 +212,19 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         sfor<0, G - 1>([&](auto g) {
             if (active) {
                 if constexpr (g > 0) {
-                    const float *lb = buf + (g & 1) * N;
+                    const float *lb = buf + (g & 1) * NP;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
                         sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = byte_at(lb, baddr[i]); });
                     } else {
-                        const int base = GMap<P, g>::base(t);
-                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+                        const int pb = GMap<P, g>::pbase(t);
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[pb + GMap<P, g>::poff(i)]; });
                     }
                 }
                 float out[ROWS];
                 group_L<P, g, SCALED>(st, st.Rtop[g], out, alpha);
-                float *lt = buf + ((g + 1) & 1) * N;
-                const int base = GMap<P, g>::base(t);
-                sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+                float *lt = buf + ((g + 1) & 1) * NP;
+                const int pb = GMap<P, g>::pbase(t);
+                sfor<0, ROWS>([&](auto i) { lt[pb + GMap<P, g>::poff(i)] = out[i]; });
             }
             boundary_sync<wave_local_boundary<P, g>(MAPPED_BOUNDARY)>();
         });
@@ -231,12 +232,12 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         // ---- last group: L pass, decision, R pass ---------------------------
         if (active) {
             if constexpr (G > 1) {
-                const float *lb = buf + ((G - 1) & 1) * N;
+                const float *lb = buf + ((G - 1) & 1) * NP;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
                     sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = byte_at(lb, baddr[i]); });
                 } else {
-                    const int base = GMap<P, G - 1>::base(t);
-                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
+                    const int pb = GMap<P, G - 1>::pbase(t);
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[pb + GMap<P, G - 1>::poff(i)]; });
                 }
             }
             group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
@@ -253,12 +254,12 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             float rb[ROWS];
             group_R<P, G - 1, SCALED>(st, prior, rb, alpha);
             if constexpr (G > 1) {
-                float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                float *rt = buf + 2 * NP + ((G - 1) & 1) * NP;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
                     sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
                 } else {
-                    const int base = GMap<P, G - 1>::base(t);
-                    sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
+                    const int pb = GMap<P, G - 1>::pbase(t);
+                    sfor<0, ROWS>([&](auto i) { rt[pb + GMap<P, G - 1>::poff(i)] = rb[i]; });
                 }
             }
             if constexpr (!GMODE) {
@@ -300,17 +301,17 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         sfor<0, G - 1>([&](auto k) {
             constexpr int g = G - 2 - k;
             if (active && !finishing) {
-                const float *rsrc = buf + 2 * N + ((g + 1) & 1) * N;
-                const int base = GMap<P, g>::base(t);
-                sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rsrc[base + GMap<P, g>::off(i)]; });
+                const float *rsrc = buf + 2 * NP + ((g + 1) & 1) * NP;
+                const int base = GMap<P, g>::base(t), pb = GMap<P, g>::pbase(t);
+                sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rsrc[pb + GMap<P, g>::poff(i)]; });
                 float rb[ROWS];
                 group_R<P, g, SCALED>(st, st.Rtop[g], rb, alpha);
                 if constexpr (g > 0) {
-                    float *rt = buf + 2 * N + (g & 1) * N;
+                    float *rt = buf + 2 * NP + (g & 1) * NP;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
                         sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
                     } else {
-                        sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                        sfor<0, ROWS>([&](auto i) { rt[pb + GMap<P, g>::poff(i)] = rb[i]; });
                     }
                 } else if constexpr (GMODE) {
                     uint32_t *X = gwords + slot * 2 * NW + NW;
