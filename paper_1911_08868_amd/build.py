@@ -34,7 +34,7 @@ def _units():
     units = []
     for n in range(1, 13):
         units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
-    for n in range(4, 11):
+    for n in range(4, 13):
         units.append((os.path.join(CSRC, "wbp_inst.hip"), f"wbp_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
     for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip"):
         lang = ["-x", "hip"] if src.endswith(".cpp") else []

@@ -1,6 +1,7 @@
 // wbp.hip -- weighted BP entry points: workspace sizing, validation, the
 // forward and adjoint launches and the deterministic reduction of the
 // per-workgroup weight-gradient partials.
+#include <algorithm>
 #include <cstring>
 
 #include "wbp_inst.h"
@@ -14,6 +15,16 @@ int run_wbp_n7(const WbpLaunch &);
 int run_wbp_n8(const WbpLaunch &);
 int run_wbp_n9(const WbpLaunch &);
 int run_wbp_n10(const WbpLaunch &);
+int run_wbp_n11(const WbpLaunch &);
+int run_wbp_n12(const WbpLaunch &);
+
+size_t wbp_big_scratch_floats(int n) {
+    if (n == 11) return BigScratch<Plan<11, 0, 2>>::per_wg_floats > BigScratch<Plan<11, 5, 2>>::per_wg_floats
+                            ? BigScratch<Plan<11, 0, 2>>::per_wg_floats : BigScratch<Plan<11, 5, 2>>::per_wg_floats;
+    if (n == 12) return BigScratch<Plan<12, 0, 2>>::per_wg_floats > BigScratch<Plan<12, 5, 2>>::per_wg_floats
+                            ? BigScratch<Plan<12, 0, 2>>::per_wg_floats : BigScratch<Plan<12, 5, 2>>::per_wg_floats;
+    return 0;
+}
 
 int launch_wbp_n(int n, const WbpLaunch &L) {
     switch (n) {
@@ -24,7 +35,9 @@ int launch_wbp_n(int n, const WbpLaunch &L) {
         case 8: return run_wbp_n8(L);
         case 9: return run_wbp_n9(L);
         case 10: return run_wbp_n10(L);
-        default: return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 1024");
+        case 11: return run_wbp_n11(L);
+        case 12: return run_wbp_n12(L);
+        default: return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 4096");
     }
 }
 
@@ -75,7 +88,7 @@ static unsigned clamp_grid(int64_t blocks) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WbpLayout {
-    size_t ckpt_bytes = 0, partial_bytes = 0, mid_bytes = 0, total = 0;
+    size_t ckpt_bytes = 0, partial_bytes = 0, mid_bytes = 0, scratch_bytes = 0, total = 0;
     int slots = 0;
     int64_t groups = 0, nchunks = 0;
 };
@@ -83,13 +96,15 @@ struct WbpLayout {
 static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
     WbpLayout w;
     w.slots = wbp_slots(c->n);
-    w.groups = (F + w.slots - 1) / w.slots;
+    const bool big = c->n >= kWbpBigLog;
+    w.groups = big ? std::min<int64_t>(F, wbp_big_grid(c->n)) : (F + w.slots - 1) / w.slots;
     w.ckpt_bytes = align256((size_t)F * (size_t)(T > 1 ? T - 1 : 0) * (size_t)(c->n - 1) * c->N * sizeof(float));
     const size_t len = (size_t)T * c->n * 2 * (size_t)c->N;
     w.partial_bytes = align256((size_t)w.groups * len * sizeof(float));
     w.nchunks = (w.groups + kGradChunk - 1) / kGradChunk;
     w.mid_bytes = w.nchunks > 1 ? align256((size_t)w.nchunks * len * sizeof(float)) : 0;
-    w.total = w.ckpt_bytes + w.partial_bytes + w.mid_bytes;
+    w.scratch_bytes = big ? align256((size_t)w.groups * wbp_big_scratch_floats(c->n) * sizeof(float)) : 0;
+    w.total = w.ckpt_bytes + w.partial_bytes + w.mid_bytes + w.scratch_bytes;
     return w;
 }
 
@@ -99,7 +114,7 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
                       const pc_pp_params *pp, void *d_ws, size_t ws_bytes, WbpLaunch &L,
                       WbpLayout &lay, bool need_ws = true) {
     if (!c) return fail(PC_EINVAL, "code is NULL");
-    if (c->n < 4 || c->n > 10) return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 1024");
+    if (c->n < 4 || c->n > 12) return fail(PC_ENOTSUP, "weighted BP is built for N = 16 .. 4096");
     if (T < 1) return fail(PC_EINVAL, "T_unroll must be >= 1");
     if (F < 0) return fail(PC_EINVAL, "F < 0");
     if (F > 0 && (!d_llr || !d_w)) return fail(PC_EINVAL, "null buffer");
@@ -130,6 +145,10 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
     a.T = T;
     a.ckpt = no_ws ? nullptr : static_cast<float *>(d_ws);
     a.partial = no_ws ? nullptr : reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes);
+    a.scratch = no_ws || !lay.scratch_bytes
+                    ? nullptr
+                    : reinterpret_cast<float *>(static_cast<char *>(d_ws) + lay.ckpt_bytes + lay.partial_bytes +
+                                                lay.mid_bytes);
     a.meta = c->d.meta;
     a.Tev = Tev;
     a.Q = Q;
@@ -137,7 +156,10 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
         for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
     L.kp = kp;
     L.slots = lay.slots;
-    L.grid = (int)lay.groups;
+    // the forward takes one workgroup per `slots` frames; the adjoint one per
+    // partial (the persistent grid for large frames)
+    L.grid = (int)((F + lay.slots - 1) / lay.slots);
+    L.bgrid = (int)lay.groups;
     return PC_OK;
 }
 
@@ -186,6 +208,7 @@ int wbp_backward(const pc_code *code, const float *d_llr, int64_t F, const float
     if (!d_grad_out) return fail(PC_EINVAL, "null output adjoint");
     L.args.gout = d_grad_out;
     L.backward = true;
+    L.grid = L.bgrid;
     L.stream = hs;
     rc = launch_wbp_n(code->n, L);
     if (rc) return rc;

@@ -10,7 +10,7 @@ struct WbpLaunch {
     WbpArgs args;
     int kp = 0;
     bool backward = false;
-    int slots = 0, grid = 0;
+    int slots = 0, grid = 0, bgrid = 0;
     hipStream_t stream = nullptr;
 };
 
@@ -20,15 +20,28 @@ inline int wbp_slots(int n) {
     return tps >= 256 ? 1 : 256 / tps;
 }
 
+// Block lengths from 2^kWbpBigLog on run the adjoint with its arrays in a
+// per-workgroup scratch (k_wbp_bwd_big) on a persistent grid of this many
+// workgroups (one per CU at N = 4096, two at N = 2048); fixed, so that the
+// order of the gradient sums does not depend on the device.
+constexpr int kWbpBigLog = 11;
+inline int wbp_big_grid(int n) { return n >= 12 ? 256 : 512; }
+size_t wbp_big_scratch_floats(int n);
+
 template <int NLOG, int KP>
 int run_wbp(const WbpLaunch &L) {
     using P = Plan<NLOG, KP, 2>;
     const int S = L.slots;
-    const size_t lds = L.backward ? WbpLds<P, true>::bytes(S) : WbpLds<P, false>::bytes(S);
+    const size_t lds = L.backward && NLOG < kWbpBigLog ? WbpLds<P, true>::bytes(S) : WbpLds<P, false>::bytes(S);
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for weighted BP");
-    if (L.backward)
-        hipLaunchKernelGGL((k_wbp_bwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);
-    else
+    if (L.backward) {
+        if constexpr (NLOG >= kWbpBigLog) {
+            const size_t big_lds = WbpLds<P, false>::bytes(1);
+            hipLaunchKernelGGL((k_wbp_bwd_big<NLOG, KP>), dim3(L.grid), dim3(P::TPS), big_lds, L.stream, L.args);
+        } else {
+            hipLaunchKernelGGL((k_wbp_bwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);
+        }
+    } else
         hipLaunchKernelGGL((k_wbp_fwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "weighted BP launch");

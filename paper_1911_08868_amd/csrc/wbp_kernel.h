@@ -43,6 +43,7 @@ struct WbpArgs {
     const float *gout;     // [F][N] adjoint of the output
     float *ckpt;           // [F][T-1][(n-1) N]
     float *partial;        // [gridDim][T][n][2][N]
+    float *scratch;        // large frames: per-workgroup arrays of the adjoint
     const int32_t *meta;   // per-row code table (frozen = -2)
     int32_t Tev, Q;
     int8_t orders[8][16];
@@ -67,18 +68,32 @@ constexpr int wbp_launch_bound() {
     return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
 }
 
-// register order of the persistent R state (checkpoint layout)
+// Checkpoint layout of the persistent R state of one frame and iteration:
+// one block per group, in group order; inside group g's block each thread's
+// gsize(g) values (the interior levels, then the top level, in register
+// order) are contiguous, so a thread moves its group with a few wide accesses
+// and consecutive threads touch consecutive memory.
 template <class P>
 struct RState {
-    static constexpr int NREG = (P::n - 1) * P::ROWS;
-    template <class Fn>
-    __device__ static __forceinline__ void each(Regs<P> &st, Fn &&fn) {
+    static constexpr int NREG = (P::n - 1) * P::ROWS;  // values per thread
+    static constexpr int gsize(int g) { return (P::size(g) - 1 + (g < P::G - 1 ? 1 : 0)) * P::ROWS; }
+    static constexpr int gstart(int g) {
         int k = 0;
+        for (int h = 0; h < g; ++h) k += gsize(h);
+        return k;
+    }
+    // element j of group g of thread t, in floats from the frame-iteration base
+    __device__ static __forceinline__ int64_t off(int g, int t, int j) {
+        return (int64_t)gstart(g) * P::TPS + (int64_t)t * gsize(g) + j;
+    }
+    template <class Fn>
+    __device__ static __forceinline__ void each(Regs<P> &st, int t, Fn &&fn) {
         sfor<0, P::G>([&](auto g) {
             sfor<0, P::size(g) - 1>([&](auto l) {
-                sfor<0, P::ROWS>([&](auto i) { fn(st.Rint[g][l][i], k); ++k; });
+                sfor<0, P::ROWS>([&](auto i) { fn(st.Rint[g][l][i], off(g, t, l * P::ROWS + i)); });
             });
-            if constexpr (g < P::G - 1) sfor<0, P::ROWS>([&](auto i) { fn(st.Rtop[g][i], k); ++k; });
+            if constexpr (g < P::G - 1)
+                sfor<0, P::ROWS>([&](auto i) { fn(st.Rtop[g][i], off(g, t, (P::size(g) - 1) * P::ROWS + i)); });
         });
     }
 };
@@ -153,13 +168,13 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
 // iteration, of the R messages it produces on its interior levels.  Adds the
 // adjoints of the L messages it read into glint/glbot, returns in gtop the
 // adjoint of the R message it read on its top level, and stages the weight
-// gradients of its stages (sweep 1) in gw[stage - lo][row].
-template <class P, int g>
+// gradients of its stages (sweep 1) through gw(stage - lo, row offset, value).
+template <class P, int g, class Sink>
 __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
                                             const float (&gbot)[P::ROWS], const float (&gstate)[P::RI][P::ROWS],
                                             float (&glint)[P::RI][P::ROWS], float (&glbot)[P::ROWS],
-                                            float (&gtop)[P::ROWS], const float *wg, float *gw, int rowbase) {
+                                            float (&gtop)[P::ROWS], const float *wg, Sink &&gw) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     float gacc[P::RI][ROWS];
     sfor<0, r - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { gacc[l][i] = gstate[l][i]; }); });
@@ -181,8 +196,8 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 const float a = l2 + r2;
                 const float g1 = ms0(r1, a), g2 = ms0(r1, l1);
-                gw[sl * N + rowbase + GMap<P, g>::off(i)] = go[i] * g1;
-                gw[sl * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * g2;
+                gw(sl, GMap<P, g>::off(i), go[i] * g1);
+                gw(sl, GMap<P, g>::off(ip), go[ip] * g2);
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
                 if (__builtin_fabsf(r1) <= __builtin_fabsf(a)) {
@@ -208,13 +223,13 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
 // it produced on its top level; glint: adjoints (already holding the R-sweep
 // contributions) of its interior L messages.  Adds to glbot, adds the
 // adjoints of the entering R state it read into gsint/gstop, stages the
-// weight gradients of its stages (sweep 0) in gw[stage - lo][row].
-template <class P, int g, bool TOPPRIOR>
+// weight gradients of its stages (sweep 0) through gw(stage - lo, row offset, value).
+template <class P, int g, bool TOPPRIOR, class Sink>
 __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
                                             const float (&gtop)[P::ROWS], float (&glint)[P::RI][P::ROWS],
                                             float (&glbot)[P::ROWS], float (&gsint)[P::RI][P::ROWS],
-                                            float (&gstop)[P::ROWS], const float *wg, float *gw, int rowbase) {
+                                            float (&gstop)[P::ROWS], const float *wg, Sink &&gw) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     sfor<0, r>([&](auto k) {
         constexpr int sl = r - 1 - k;
@@ -234,8 +249,8 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 const float a = l2 + r2;
                 const float f1 = ms0(l1, a), f2 = ms0(r1, l1);
-                gw[sl * N + rowbase + GMap<P, g>::off(i)] = go[i] * f1;
-                gw[sl * N + rowbase + GMap<P, g>::off(ip)] = go[ip] * f2;
+                gw(sl, GMap<P, g>::off(i), go[i] * f1);
+                gw(sl, GMap<P, g>::off(ip), go[ip] * f2);
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
                 if (__builtin_fabsf(l1) <= __builtin_fabsf(a)) {
@@ -319,8 +334,8 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
             }
         }
         if (it > 0 && active && a.ckpt) {
-            float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS + t;
-            RState<P>::each(st, [&](float &v, int k) { ck[(int64_t)k * TPS] = v; });
+            float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS;
+            RState<P>::each(st, t, [&](float &v, int64_t o) { ck[o] = v; });
         }
         const float *wt = a.w + (int64_t)it * n * 2 * N;
         sfor<0, G - 1>([&](auto g) {
@@ -461,10 +476,10 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
             }
             // entering R state
             if (it == 0) {
-                RState<P>::each(st, [&](float &v, int k) { v = 0.f; });
+                RState<P>::each(st, t, [&](float &v, int64_t) { v = 0.f; });
             } else {
-                const float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS + t;
-                RState<P>::each(st, [&](float &v, int k) { v = ck[(int64_t)k * TPS]; });
+                const float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS;
+                RState<P>::each(st, t, [&](float &v, int64_t o) { v = ck[o]; });
             }
             // a trellis switch after this iteration reset the inner levels of
             // the permuted range: nothing flows back through them
@@ -551,8 +566,9 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                         else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
                     }
                     float gtop[ROWS];
+                    float *const gws = buf + 4 * N + (g & 1) * RHO * N + base;
                     rev_group_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                      wt + base, buf + 4 * N + (g & 1) * RHO * N, base);
+                                      wt + base, [&](int sl, int off, float v) { gws[sl * N + off] = v; });
                     if constexpr (g < G - 1) {
                         float *dst = buf + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
@@ -583,12 +599,12 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                     if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
                     else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
                     rev_group_L<P, g, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g], gsi[g],
-                                            gst[g], wt + base, gws, base);
+                                            gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * N + base + off] = v; });
                 } else {
                     const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
                     rev_group_L<P, g, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g], glb[g],
-                                             gsi[g], gst[g], wt + base, gws, base);
+                                             gsi[g], gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * N + base + off] = v; });
                 }
                 if constexpr (g > 0) {
                     float *dst = buf + 2 * N + (g & 1) * N;
@@ -605,6 +621,240 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
             for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large frames (N >= 2048, one frame of 512 or 1024 threads per workgroup).
+// The adjoint's per-thread arrays (entering R state, L and R sweep messages,
+// two adjoint sets) exceed the registers a thread of such a workgroup can
+// hold, so this kernel keeps one group's arrays in registers at a time and
+// streams the rest through a per-workgroup scratch in global memory, stored
+// in the thread's register order: coalesced, and each thread reads back only
+// what it wrote, so no barrier orders the scratch.  The four phases of an
+// iteration (recompute L, recompute R, reverse R, reverse L) are those of
+// k_wbp_bwd.  A persistent grid of fixed size walks the frames; each thread
+// adds its own weight-gradient entries into its workgroup's partial in frame
+// order (the workgroup's first frame stores), so the result does not depend
+// on scheduling.
+template <class P>
+struct BigScratch {
+    static constexpr int GE = (P::RI + 1) * P::ROWS;                  // floats per thread per group
+    static constexpr size_t ASZ = (size_t)P::G * P::TPS * GE;         // floats per array
+    static constexpr size_t per_wg_floats = 4 * ASZ;                  // [array][group][thread][GE]
+};
+
+template <int NLOG, int KP>
+__global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
+    using P = Plan<NLOG, KP, 2>;
+    constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG, GB = P::GB, RI = P::RI;
+    constexpr bool MAPPED = (KP > 0 && KP < NLOG);
+    constexpr int LOWBITS = NLOG - KP;
+    constexpr int NREG = RState<P>::NREG;
+    constexpr int GE = BigScratch<P>::GE;
+    constexpr size_t ASZ = BigScratch<P>::ASZ;
+    const int t = threadIdx.x;
+    extern __shared__ __align__(16) float smem[];
+    float *const buf = smem;  // [A0 A1 | B0 B1]
+    int8_t *const ords = reinterpret_cast<int8_t *>(smem + 4 * N);
+    for (int i = t; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i >> 4][i & 15];
+    __syncthreads();
+
+    float *const scr = a.scratch + (size_t)blockIdx.x * BigScratch<P>::per_wg_floats;
+    // scratch arrays: L messages, R sweep messages, adjoint of the R state,
+    // adjoint of the L messages; a thread's block of group g holds the
+    // interior levels l < RI and, at l = RI, the bottom level (L and its
+    // adjoint) or the top level (R sweep, adjoint of the R state)
+    enum { LS = 0, RS = 1, GS = 2, GL = 3 };
+    // The thread index is passed through an empty asm at every group step:
+    // otherwise the compiler hoists every block address out of the frame
+    // and iteration loops and runs out of registers.
+    auto tid_here = [&]() {
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+        return tt;
+    };
+    auto blk = [&](int arr, int g, int tt) { return scr + arr * ASZ + ((size_t)g * TPS + tt) * GE; };
+    auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
+    float *const part = a.partial + (size_t)blockIdx.x * a.T * n * 2 * N;
+
+    for (int64_t frame = blockIdx.x; frame < a.F; frame += gridDim.x) {
+        const bool first = frame == (int64_t)blockIdx.x;
+        for (int it = a.T - 1; it >= 0; --it) {
+            const int q = order_at(it);
+            const bool lastit = (it == a.T - 1);
+            const bool reset_next = KP > 0 && !lastit && order_at(it + 1) != q;
+            const float *wt = a.w + (int64_t)it * n * 2 * N;
+            float *const pt = part + (size_t)it * n * 2 * N;
+            const float *ck = it > 0 ? a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS : nullptr;
+            int baddr[ROWS], toprow[ROWS];
+            float prior[ROWS];
+            {
+                const int8_t *e = ords + q * 16;
+                const int base = GMap<P, G - 1>::base(t);
+                sfor<0, ROWS>([&](auto i) {
+                    const int p = base + GMap<P, G - 1>::off(i);
+                    const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+                    toprow[i] = j;
+                    prior[i] = a.meta[j] == -2 ? kWbpPrior : 0.f;
+                });
+                if constexpr (MAPPED) {
+                    const int bb = GMap<P, GB>::base(t);
+                    sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
+                }
+            }
+            // accumulate a weight gradient of stage lo + sl, sweep d, row base + off
+            auto sink = [&](int lo, int d, int base) {
+                return [=](int sl, int off, float v) {
+                    float *p = pt + ((lo + sl) * 2 + d) * N + base + off;
+                    *p = first ? v : *p + v;
+                };
+            };
+            auto load_state = [&](auto gc, float (&rint)[RI][ROWS], float (&rtop)[ROWS]) {
+                constexpr int g = decltype(gc)::value;
+                if (ck) {
+                    const float *b = ck + RState<P>::off(g, tid_here(), 0);
+                    sfor<0, P::size(g) - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { rint[l][i] = b[l * ROWS + i]; }); });
+                    if constexpr (g < G - 1)
+                        sfor<0, ROWS>([&](auto i) { rtop[i] = b[(P::size(g) - 1) * ROWS + i]; });
+                } else {
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { rint[l][i] = 0.f; }); });
+                    if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { rtop[i] = 0.f; });
+                }
+                if constexpr (g == G - 1) sfor<0, ROWS>([&](auto i) { rtop[i] = prior[i]; });
+            };
+            auto load2 = [&](int arr, auto gc, float (&x)[RI][ROWS], float (&y)[ROWS]) {
+                constexpr int g = decltype(gc)::value;
+                const float *b = blk(arr, g, tid_here());
+                sfor<0, P::size(g) - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { x[l][i] = b[l * ROWS + i]; }); });
+                sfor<0, ROWS>([&](auto i) { y[i] = b[RI * ROWS + i]; });
+            };
+            auto store2 = [&](int arr, auto gc, const float (&x)[RI][ROWS], const float (&y)[ROWS]) {
+                constexpr int g = decltype(gc)::value;
+                float *b = blk(arr, g, tid_here());
+                sfor<0, P::size(g) - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { b[l * ROWS + i] = x[l][i]; }); });
+                sfor<0, ROWS>([&](auto i) { b[RI * ROWS + i] = y[i]; });
+            };
+
+            // ---- recompute the L sweep (groups 0..G-1) ----
+            sfor<0, G>([&](auto g) {
+                const int base = GMap<P, g>::base(t);
+                float lbot[ROWS], lint[RI][ROWS], rint[RI][ROWS], rtop[ROWS], out[ROWS];
+                if constexpr (g == 0) {
+                    const float *src = a.llr + frame * N;
+                    sfor<0, ROWS>([&](auto i) { lbot[i] = src[base + GMap<P, 0>::off(i)]; });
+                } else {
+                    const float *lb = buf + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { lbot[i] = lb[baddr[i]]; });
+                    else sfor<0, ROWS>([&](auto i) { lbot[i] = lb[base + GMap<P, g>::off(i)]; });
+                }
+                load_state(g, rint, rtop);
+                wgroup_L<P, g>(lbot, lint, rint, rtop, out, wt + base);
+                store2(LS, g, lint, lbot);
+                if constexpr (g < G - 1) {
+                    float *lt = buf + ((g + 1) & 1) * N;
+                    sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+                }
+                __syncthreads();
+            });
+            if (!lastit) {
+                // ---- recompute the R sweep (groups G-1..0), keeping every level ----
+                sfor<0, G>([&](auto k) {
+                    constexpr int g = G - 1 - k;
+                    const int base = GMap<P, g>::base(t);
+                    float lbot[ROWS], lint[RI][ROWS], rsw[RI][ROWS], rtop[ROWS], rb[ROWS];
+                    load2(LS, std::integral_constant<int, g>{}, lint, lbot);
+                    if constexpr (g == G - 1) {
+                        sfor<0, ROWS>([&](auto i) { rtop[i] = prior[i]; });
+                    } else {
+                        const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
+                        sfor<0, ROWS>([&](auto i) { rtop[i] = rs[base + GMap<P, g>::off(i)]; });
+                    }
+                    wgroup_R<P, g>(lbot, lint, rsw, rtop, rb, wt + base);
+                    store2(RS, std::integral_constant<int, g>{}, rsw, rtop);
+                    if constexpr (g > 0) {
+                        float *rt = buf + 2 * N + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                        else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                    }
+                    __syncthreads();
+                });
+                // ---- reverse of the R sweep (groups 0..G-1) ----
+                sfor<0, G>([&](auto g) {
+                    const int base = GMap<P, g>::base(t);
+                    float lbot[ROWS], lint[RI][ROWS], rsw[RI][ROWS], rtsw[ROWS], gsi[RI][ROWS], gst[ROWS];
+                    float gli[RI][ROWS], glb[ROWS], gb[ROWS], gtop[ROWS];
+                    load2(LS, g, lint, lbot);
+                    load2(RS, g, rsw, rtsw);
+                    // the adjoint of the R state leaving this iteration; a trellis
+                    // switch after it reset the inner levels of the permuted range
+                    load2(GS, g, gsi, gst);
+                    if constexpr (KP > 0 && g >= GB) {
+                        if (reset_next) {
+                            sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[l][i] = 0.f; }); });
+                            sfor<0, ROWS>([&](auto i) { gst[i] = 0.f; });
+                        }
+                    }
+                    if constexpr (g == 0) {
+                        sfor<0, ROWS>([&](auto i) { gb[i] = 0.f; });
+                    } else {
+                        const float *src = buf + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { gb[i] = src[baddr[i]]; });
+                        else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
+                    }
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = 0.f; }); });
+                    sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
+                    rev_group_R<P, g>(lbot, lint, rsw, rtsw, gb, gsi, gli, glb, gtop, wt + base,
+                                      sink(P::lo(g), 1, base));
+                    store2(GL, g, gli, glb);
+                    if constexpr (g < G - 1) {
+                        float *dst = buf + ((g + 1) & 1) * N;
+                        sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[i]; });
+                    }
+                    __syncthreads();
+                });
+            } else {
+                // the last iteration runs no R sweep: its R weights get no gradient
+                if (first) {
+                    for (int idx = t; idx < n * N; idx += blockDim.x) pt[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
+                }
+            }
+            // ---- reverse of the L sweep (groups G-1..0) ----
+            sfor<0, G>([&](auto k) {
+                constexpr int g = G - 1 - k;
+                const int base = GMap<P, g>::base(t);
+                float lbot[ROWS], lint[RI][ROWS], rint[RI][ROWS], rtop[ROWS], gli[RI][ROWS], glb[ROWS];
+                float gsi[RI][ROWS], gst[ROWS], gt[ROWS];
+                load2(LS, std::integral_constant<int, g>{}, lint, lbot);
+                load_state(std::integral_constant<int, g>{}, rint, rtop);
+                if (lastit) {
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = 0.f; }); });
+                    sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
+                } else {
+                    load2(GL, std::integral_constant<int, g>{}, gli, glb);
+                }
+                sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[l][i] = 0.f; }); });
+                sfor<0, ROWS>([&](auto i) { gst[i] = 0.f; });
+                if constexpr (g == G - 1) {
+                    if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
+                    else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
+                    rev_group_L<P, g, true>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
+                                            sink(P::lo(g), 0, base));
+                } else {
+                    const float *src = buf + 2 * N + ((g + 1) & 1) * N;
+                    sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
+                    rev_group_L<P, g, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
+                                             sink(P::lo(g), 0, base));
+                }
+                store2(GS, std::integral_constant<int, g>{}, gsi, gst);
+                if constexpr (g > 0) {
+                    float *dst = buf + 2 * N + (g & 1) * N;
+                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { dst[baddr[i]] = glb[i]; });
+                    else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[i]; });
+                }
+                __syncthreads();
+            });
+        }
     }
 }
 

@@ -124,6 +124,47 @@ def test_autograd_training_step(orc, pbp):
     assert abs(loss.item() - l2.item()) < 1e-5 * max(1.0, abs(l2.item()))
 
 
+@pytest.mark.parametrize("N,K,T,F,pp", [(2048, 1024, 3, 5, None), (2048, 1100, 4, 3, (5, 1, 4)),
+                                        (4096, 2048, 3, 3, (5, 1, 8)), (4096, 2072, 2, 3, None)])
+def test_weighted_large_frames(orc, pbp, N, K, T, F, pp):
+    # N >= 2048: one frame per workgroup, the adjoint streams its arrays
+    # through a per-workgroup scratch
+    n = N.bit_length() - 1
+    oc, u, llr = _setup(orc, N, K, F, seed=N + T)
+    rng = np.random.default_rng(T)
+    w = rng.uniform(0.7, 1.3, (T, n, 2, N)).astype(np.float32).astype(np.float64)
+    gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
+    gout[:, oc.frozen.astype(bool)] = 0.0
+    if pp:
+        k, tev, Q = pp
+        opp = orc.WbpParams(pp_mode=orc.PP_LASTK, k=k, T_ev=tev, Q=Q, seed=3, fp32=True)
+        gpp = pbp.PPParams(mode=pbp.PP_LASTK, k=k, period_T=tev, pool_Q=Q, seed=3)
+    else:
+        opp, gpp = orc.WbpParams(fp32=True), None
+    out, gw = _gpu(pbp, oc, llr, w, T, gpp, gout)
+    assert np.array_equal(out.view(np.uint32), orc.wbp_forward(oc, llr, w, opp).astype(np.float32).view(np.uint32))
+    ref_gw, _ = orc.wbp_backward(oc, llr, w, opp, gout)
+    np.testing.assert_allclose(gw, ref_gw, rtol=0, atol=_grad_tol(ref_gw))
+    assert np.all(gw[T - 1, :, 1] == 0.0)
+
+
+def test_weighted_large_frames_more_than_the_grid(orc, pbp):
+    # 260 frames on the 256-workgroup grid: four workgroups take a second
+    # frame and add into their partial
+    N, K, T, F = 4096, 2048, 2, 260
+    oc, u, llr = _setup(orc, N, K, F, seed=12)
+    rng = np.random.default_rng(12)
+    w = rng.uniform(0.8, 1.2, (T, 12, 2, N)).astype(np.float32).astype(np.float64)
+    gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
+    out, gw = _gpu(pbp, oc, llr, w, T, None, gout)
+    opp = orc.WbpParams(fp32=True)
+    assert np.array_equal(out.view(np.uint32), orc.wbp_forward(oc, llr, w, opp).astype(np.float32).view(np.uint32))
+    ref_gw, _ = orc.wbp_backward(oc, llr, w, opp, gout)
+    np.testing.assert_allclose(gw, ref_gw, rtol=0, atol=_grad_tol(ref_gw))
+    again = _gpu(pbp, oc, llr, w, T, None, gout)[1]
+    assert np.array_equal(gw.view(np.uint32), again.view(np.uint32))
+
+
 @pytest.mark.parametrize("N,K,T,F", [(64, 32, 3, 16 * 70 + 5), (16, 8, 2, 64 * 65 + 3)])
 def test_weighted_gradient_over_many_workgroups(orc, pbp, N, K, T, F):
     # more than 64 workgroup partials: both levels of the gradient reduction
