@@ -6,6 +6,9 @@ frame, binary cross entropy of the output LLRs against the transmitted
 information bits) timed forward + backward + SGD step, next to plain min-sum
 BP decoding of the same frames.
 
+weighted_bp_large(): the same at N=4096 with the last-5 trellis schedule and
+20 unrolled iterations, beside unit-weight PP-MT-BP decoding.
+
 batched_mixed(): the mixed-length stream through the persistent queue kernel
 (see batched.py).
 """
@@ -95,10 +98,93 @@ def weighted_bp(torch, pbp, steps=5, warmup=2, F=16384, T=10):
             "fer_weighted_after_steps": fer_w, "fer_plain": fer_p}
 
 
+def weighted_bp_large(torch, pbp, F_train=1024, F_dec=8192, T=20, steps=2, warmup=1):
+    """Weighted PP-MT-BP at scale: N=4096, K=2048 + CRC-24 (K=2072), the last 5
+    of 12 stages re-ordered every 10 iterations from 8 trellises, 20 unrolled
+    iterations with weights tied across trellises, Eb/N0 ~ U[1,3] dB.  Timed:
+    a training step (forward with checkpoints, adjoint, gradient-norm clip,
+    SGD) on F_train frames,
+    the weighted forward alone on F_dec frames, and unit-weight PP-MT-BP
+    (CRC stop, same iteration budget) on the same frames."""
+    import synth
+    from .wbp import WeightedBPDecoder, bce_on_information_bits
+    code = pbp.Code(4096, 2072, 24, 0x1864CFB, 2.5)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=5, period_T=10, pool_Q=8, seed=1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(91)
+    F = max(F_train, F_dec)
+    m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+    x = pbp.encode(code, m)
+    ebn0 = torch.rand(F, generator=gen, device="cuda", dtype=torch.float64) * 2.0 + 1.0
+    llr = synth.awgn_llr_torch(x, ebn0, code.K_msg, gen)
+    u = polar_transform_torch(x, code.n)
+    info = torch.from_numpy(code.info_idx.astype("int64")).cuda()
+    u_info = u[:, info]
+    dec = WeightedBPDecoder(code, T, pp)
+    opt = torch.optim.SGD(dec.parameters(), lr=1e-2)
+    xt, ut = llr[:F_train], u_info[:F_train]
+
+    def step():
+        out = dec(xt)
+        loss = bce_on_information_bits(out, ut, info)
+        opt.zero_grad(set_to_none=False)
+        loss.backward()
+        # Over 20 unrolled min-sum iterations the gradient of the earliest
+        # iterations' weights can explode (every message fans out into later
+        # ones while each check node routes its adjoint to one input; the
+        # FP64 oracle gives entries up to ~1e15 on such frames), so the step
+        # clips the gradient norm.
+        torch.nn.utils.clip_grad_norm_(dec.parameters(), 1.0)
+        opt.step()
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        loss = step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_train = a.elapsed_time(b) / steps
+    xd = llr[:F_dec]
+    with torch.no_grad():
+        o = dec(xd)
+        torch.cuda.synchronize()
+        a.record()
+        o = dec(xd)
+        b.record()
+        torch.cuda.synchronize()
+    ms_fwd = a.elapsed_time(b)
+    fer_w = ((o[:, info] < 0).to(torch.uint8) != u_info[:F_dec]).any(1).double().mean().item()
+    bp = pbp.BPParams(max_iter=T, stop=pbp.STOP_CRC, it_min=3)
+    outs = pbp.pp_mt_bp_decode(code, xd, bp, pp)
+    torch.cuda.synchronize()
+    a.record()
+    outs = pbp.pp_mt_bp_decode(code, xd, bp, pp, out=outs[:3])
+    b.record()
+    torch.cuda.synchronize()
+    ms_unit = a.elapsed_time(b)
+    fer_u = (outs[0] != m[:F_dec]).any(1).double().mean().item()
+    _log(f"weighted BP N=4096: train step {ms_train:.1f} ms ({F_train} frames), forward {ms_fwd:.1f} ms, "
+         f"unit-weight PP-MT-BP {ms_unit:.1f} ms ({F_dec} frames)")
+    return {"workload": f"weighted PP-MT-BP, N=4096 K=2048+CRC24, last 5 of 12 stages every 10 iterations "
+                        f"(Q=8, weights tied across trellises), {T} unrolled iterations, Eb/N0 ~ U[1,3] dB; "
+                        f"training batch {F_train}, decode {F_dec} frames",
+            "train_frames_s": round(F_train / (ms_train / 1e3), 1), "ms_train_step": round(ms_train, 2),
+            "fwd_frames_s": round(F_dec / (ms_fwd / 1e3), 1),
+            "unit_pp_mt_bp_frames_s": round(F_dec / (ms_unit / 1e3), 1),
+            "loss": round(float(loss.item()), 5),
+            "fer_weighted_after_steps": fer_w, "fer_unit_pp_mt_bp": fer_u,
+            "avg_iters_unit": round(outs[1].double().mean().item(), 3)}
+
+
 def bench_extras(torch, pbp):
     from .batched import bench_mixed
     out = {}
-    for name, fn in (("weighted_bp", weighted_bp), ("batched_mixed", bench_mixed)):
+    for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
+                     ("batched_mixed", bench_mixed)):
         try:
             out[name] = fn(torch, pbp)
         except Exception as e:  # report the failure in the JSON line, keep the rest
