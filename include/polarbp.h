@@ -46,8 +46,8 @@ extern "C" {
 #define PC_PP_LASTK 0   /* last k stages re-ordered from a seeded pool every T iters  */
 #define PC_PP_FULL 1    /* all n stages re-ordered: multi-trellis BP with full
                            permutations (Sec. II-D); only L_1 and R_{n+1} survive     */
-#define PC_PP_ALG1 2    /* Algorithm 1's random subgraph per event: not implemented
-                           on the GPU (returns PC_ENOTSUP)                            */
+#define PC_PP_ALG1 2    /* Algorithm 1: a random subgraph re-ordered per event, the
+                           events spaced by Eq. 2 (see pc_pp_params)                  */
 
 /* Opaque polar code: frozen set, CRC, and device copies of the per-row
  * tables the decoder reads.  Immutable after construction; may be shared by
@@ -77,9 +77,25 @@ typedef struct {
     int32_t k;        /* permuted stages, 2 <= k <= n (LASTK)                */
     int32_t period_T; /* iterations between permutations, >= 1               */
     int32_t pool_Q;   /* pool size, 1 <= Q <= 8                              */
-    int32_t P_range, P_level, D, N_min, first_reset; /* ALG1 (unsupported)   */
+    int32_t P_range, P_level, D, N_min, first_reset; /* ALG1, below         */
     uint64_t seed;
 } pc_pp_params;
+/* PC_PP_ALG1 (Algorithm 1, Sec. III and Table I).  At an event a frame draws
+ * rho_range ~ U{2..P_range}, rho_level = min(U{1..P_level}, n - rho_range + 1)
+ * and one of the N/2^m connected blocks of stages 1..m of its current graph
+ * (m = rho_level + rho_range - 1, blocks ranked by their smallest row); stages
+ * rho_level..m of that block get a new non-identity order of the bits they
+ * use, and the block's nodes on the levels strictly between them are reset.
+ * A draw whose block is not 2^m rows or whose stages do not each use one bit
+ * over it is drawn again (at most 64 times; then the event is skipped).  The
+ * draws come from SplitMix64 seeded with seed + (frame + 1) * 0x9E3779B97F4A7C15.
+ * The first event follows iteration first_reset (0: min(max(N_min,
+ * floor(N (n-1) / D)), floor(max_iter / 2))); each later one follows
+ * iteration it + max(N_min, floor(N_zero / D)) with N_zero = 2^m (rho_range-1)
+ * of the previous event (0 if skipped; D = 0 gives N_min).  Needs
+ * 2 <= P_range <= n, 1 <= P_level <= n-1, N_min >= 1.  On the GPU: N = 16 ..
+ * 1024, codes with a CRC and PC_STOP_CRC or PC_STOP_NONE; one frame per
+ * workgroup with every message in LDS, so no launch configuration.         */
 
 /* Launch configuration picked by the autotuner; NULL selects the library's
  * table.  rho: log2 rows held per thread per level (2 or 3); slots: frames

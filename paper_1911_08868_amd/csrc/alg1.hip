@@ -1,0 +1,353 @@
+// alg1.hip -- Algorithm 1 (partially permuted BP with random subgraphs) on
+// the GPU: one frame per workgroup, messages in LDS, a per-row stage order.
+//
+// Algorithm 1 permutes one subgraph at a time: at an event it draws a range
+// rho_range in {2..P_range}, a level rho_level = min(U{1..P_level},
+// n - rho_range + 1) and one of the N / 2^m connected blocks of stages 1..m
+// of the current graph (m = rho_level + rho_range - 1), and gives stages
+// rho_level..m of that block a new non-identity order of the bits they use;
+// the nodes on the levels strictly between the permuted stages of the block
+// are reset, and the next event follows Eq. 2 (iteration + max(N_min,
+// floor(N_zero / D)), N_zero = 2^m (rho_range - 1)).  A draw is kept only if
+// the component has 2^m rows and each of the stages uses one bit over it (so
+// every graph still encodes x = u G_N); otherwise it is drawn again, at most
+// 64 times.  Rows of different blocks then pair on different bits, so the
+// relabelled, register-resident layout of k_decode does not apply: here every
+// row carries its own order (N x n bytes in LDS) and all L and R levels live
+// in LDS, (2n+1) N floats.
+//
+// Each stage is row-parallel: a thread visits rows tid, tid + blockDim, ...;
+// a row that is the top of its pair for that stage (its pairing bit is 0)
+// computes the processing element (Sec. II-B) and writes both outputs.
+// Stages are separated by workgroup barriers.  The random draws come from a
+// SplitMix64 stream per frame (seed + (frame + 1) * golden ratio, as in the
+// CPU reference decoder) that every thread advances identically, so all
+// control decisions are uniform.  The component labels of stages 1..m are
+// found by propagating the smallest row index over the pairs until nothing
+// changes; blocks are ranked by their smallest row.
+#include <climits>
+
+#include "bp_core.h"
+#include "internal.h"
+
+namespace pbp {
+
+struct Alg1Args {
+    const float *llr;
+    int64_t F;
+    uint8_t *msg;
+    int32_t *iters;
+    uint8_t *ok;
+    float *soft;
+    const uint32_t *syn;
+    const int32_t *meta;
+    uint32_t *counter;
+    int32_t K_msg, max_iter, it_min, stop;
+    float alpha;
+    int32_t P_range, P_level, D, N_min, first_reset;
+    uint64_t seed;
+};
+
+__device__ __forceinline__ uint64_t splitmix64_next(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// uniform integer in [0, m): the high 32 bits of the next output, scaled by m
+__device__ __forceinline__ uint32_t draw_below(uint64_t &s, uint32_t m) {
+    const uint64_t hi = splitmix64_next(s) >> 32;
+    return (uint32_t)((hi * (uint64_t)m) >> 32);
+}
+
+template <int NLOG>
+struct Alg1Lds {
+    static constexpr int N = 1 << NLOG, n = NLOG;
+    static constexpr size_t msg_floats = (size_t)(2 * n + 1) * N;  // L levels 0..n, R levels 1..n
+    static constexpr size_t ord_bytes = ((size_t)N * n + 15) & ~(size_t)15;
+    static constexpr size_t bytes = msg_floats * 4 + ord_bytes + (size_t)N * 4 + 64 * 4;
+};
+
+template <int NLOG, bool SCALED>
+__global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
+    constexpr int N = 1 << NLOG, n = NLOG;
+    using Lay = Alg1Lds<NLOG>;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    extern __shared__ __align__(16) float smem[];
+    float *const Lm = smem;                  // level l at Lm + l N, l = 0..n
+    float *const Rm = smem + (size_t)(n + 1) * N - N;  // level l at Rm + l N, l = 1..n
+    int8_t *const ord = reinterpret_cast<int8_t *>(smem + Lay::msg_floats);  // [N][n]
+    int32_t *const lab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ord) + Lay::ord_bytes);
+    int32_t *const misc = lab + N;           // [0] frame, [1] flag, [2] count, [3] root, [4..] wave partials
+    const float alpha = a.alpha;
+    const float inf = __builtin_huge_valf();
+    auto Lv = [&](int l, int j) -> float & { return Lm[(size_t)l * N + j]; };
+    auto Rv = [&](int l, int j) -> float & { return Rm[(size_t)l * N + j]; };
+
+    // workgroup-wide or / sum of per-thread values (includes the barriers)
+    auto wg_or = [&](bool v) -> bool {
+        __syncthreads();
+        if (tid == 0) misc[1] = 0;
+        __syncthreads();
+        if (v) misc[1] = 1;
+        __syncthreads();
+        return misc[1] != 0;
+    };
+    auto wg_xor = [&](uint32_t v) -> uint32_t {
+        v = lanes_xor<64>(v);
+        __syncthreads();
+        if ((tid & 63) == 0) misc[4 + (tid >> 6)] = (int32_t)v;
+        __syncthreads();
+        uint32_t s = 0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) s ^= (uint32_t)misc[4 + w];
+        return s;
+    };
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) misc[0] = (int32_t)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int64_t frame = misc[0];
+        if (frame >= a.F) break;
+
+        // ---- initialise L and R (Alg. 1 initializeLandR) and the orders ----
+        const float *src = a.llr + frame * N;
+        for (int j = tid; j < N; j += nt) {
+            Lv(0, j) = src[j];
+            for (int l = 1; l <= n; ++l) Lv(l, j) = 0.f;
+            for (int l = 1; l < n; ++l) Rv(l, j) = 0.f;
+            Rv(n, j) = a.meta[j] == -2 ? inf : 0.f;
+            for (int s = 0; s < n; ++s) ord[j * n + s] = (int8_t)s;
+        }
+        uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
+        int next_reset;
+        if (a.first_reset > 0) {
+            next_reset = a.first_reset;
+        } else {
+            const int full = a.D > 0 ? (N * (n - 1)) / a.D : 0;
+            const int v = full > a.N_min ? full : a.N_min;
+            next_reset = v < a.max_iter / 2 ? v : a.max_iter / 2;
+        }
+        __syncthreads();
+
+        int it_done = a.max_iter;
+        bool okv = false;
+        for (int it = 1; it <= a.max_iter; ++it) {
+            // ---- L sweep, stages 1..n ----
+            for (int s = 1; s <= n; ++s) {
+                for (int j = tid; j < N; j += nt) {
+                    const int b = ord[j * n + s - 1];
+                    if ((j >> b) & 1) continue;
+                    const int jp = j | (1 << b);
+                    const float l1 = Lv(s - 1, j), l2 = Lv(s - 1, jp), r1 = Rv(s, j), r2 = Rv(s, jp);
+                    Lv(s, j) = cnode<SCALED>(l1, l2 + r2, alpha);
+                    Lv(s, jp) = cnode<SCALED>(r1, l1, alpha) + l2;
+                }
+                __syncthreads();
+            }
+            // ---- decision and CRC syndrome on level n+1 ----
+            uint32_t syn = 0;
+            for (int j = tid; j < N; j += nt) {
+                const float v = Lv(n, j) + Rv(n, j);
+                if (v < 0.f) syn ^= a.syn[j];
+            }
+            const bool pass = wg_xor(syn) == 0u;
+            if (a.stop == PC_STOP_CRC && it >= a.it_min && pass) {
+                it_done = it;
+                okv = true;
+                break;
+            }
+            if (it == a.max_iter) {
+                okv = pass;
+                break;
+            }
+            // ---- R sweep, stages n..2 (R on the channel level is never read) ----
+            for (int s = n; s >= 2; --s) {
+                for (int j = tid; j < N; j += nt) {
+                    const int b = ord[j * n + s - 1];
+                    if ((j >> b) & 1) continue;
+                    const int jp = j | (1 << b);
+                    const float l1 = Lv(s - 1, j), l2 = Lv(s - 1, jp), r1 = Rv(s, j), r2 = Rv(s, jp);
+                    Rv(s - 1, j) = cnode<SCALED>(r1, l2 + r2, alpha);
+                    Rv(s - 1, jp) = cnode<SCALED>(r1, l1, alpha) + r2;
+                }
+                __syncthreads();
+            }
+            // ---- partial permutation of one subgraph (Alg. 1 partialPermute) ----
+            if (it == next_reset) {
+                int n_zero = 0;
+                for (int attempt = 0; attempt < 64; ++attempt) {
+                    const int rr = 2 + (int)draw_below(st, (uint32_t)(a.P_range - 1));
+                    const int x = 1 + (int)draw_below(st, (uint32_t)a.P_level);
+                    const int rl = x < n - rr + 1 ? x : n - rr + 1;
+                    const int m = rl + rr - 1;
+                    const int nblocks = N >> m;
+                    const int blk = (int)draw_below(st, (uint32_t)nblocks);
+                    // components of stages 1..m: smallest row index by propagation
+                    for (int j = tid; j < N; j += nt) lab[j] = j;
+                    bool changed = true;
+                    while (changed) {
+                        bool c = false;
+                        __syncthreads();
+                        for (int j = tid; j < N; j += nt) {
+                            int v = lab[j];
+                            for (int s = 1; s <= m; ++s) {
+                                const int p = j ^ (1 << ord[j * n + s - 1]);
+                                const int w = lab[p];
+                                v = w < v ? w : v;
+                            }
+                            if (v < lab[j]) {
+                                lab[j] = v;
+                                c = true;
+                            }
+                        }
+                        changed = wg_or(c);
+                    }
+                    // number of components and the root of rank blk
+                    __syncthreads();
+                    if (tid == 0) {
+                        int cnt = 0, root = -1;
+                        for (int j = 0; j < N; ++j) {
+                            if (lab[j] == j) {
+                                if (cnt == blk) root = j;
+                                ++cnt;
+                            }
+                        }
+                        misc[2] = cnt;
+                        misc[3] = root;
+                    }
+                    __syncthreads();
+                    if (misc[2] != nblocks) continue;
+                    const int root = misc[3];
+                    // size of the block and one bit per permuted stage over it
+                    int members = 0;
+                    bool mixed = false;
+                    for (int j = tid; j < N; j += nt) {
+                        if (lab[j] != root) continue;
+                        ++members;
+                        for (int s = rl; s <= m; ++s) mixed |= ord[j * n + s - 1] != ord[root * n + s - 1];
+                    }
+                    __syncthreads();
+                    if (tid == 0) misc[2] = 0;
+                    __syncthreads();
+                    if (members) atomicAdd(&misc[2], members);
+                    const bool bad = wg_or(mixed);
+                    if (bad || misc[2] != (1 << m)) continue;
+                    // a new non-identity order of the bits of stages rl..m
+                    int8_t bits[kMaxLog], cand[kMaxLog];
+                    for (int i = 0; i < rr; ++i) bits[i] = ord[root * n + rl - 1 + i];
+                    bool ident = true;
+                    while (ident) {
+                        for (int i = 0; i < rr; ++i) cand[i] = bits[i];
+                        for (int i = rr - 1; i >= 1; --i) {
+                            const int jj = (int)draw_below(st, (uint32_t)(i + 1));
+                            const int8_t tt = cand[i];
+                            cand[i] = cand[jj];
+                            cand[jj] = tt;
+                        }
+                        ident = true;
+                        for (int i = 0; i < rr; ++i) ident &= cand[i] == bits[i];
+                    }
+                    __syncthreads();  // every thread has read the old orders of the root
+                    for (int j = tid; j < N; j += nt) {
+                        if (lab[j] != root) continue;
+                        for (int i = 0; i < rr; ++i) ord[j * n + rl - 1 + i] = cand[i];
+                        // levels strictly between the permuted stages (Sec. III)
+                        for (int l = rl; l <= m - 1; ++l) {
+                            Lv(l, j) = 0.f;
+                            Rv(l, j) = 0.f;
+                        }
+                    }
+                    n_zero = (1 << m) * (rr - 1);
+                    break;
+                }
+                int add = a.D > 0 ? n_zero / a.D : 0;
+                if (add < a.N_min) add = a.N_min;
+                next_reset = it + add;
+                __syncthreads();
+            }
+        }
+
+        // ---- outputs (Alg. 1 hardDecision) ----
+        uint8_t *mo = a.msg + frame * a.K_msg;
+        for (int j = tid; j < N; j += nt) {
+            const int mi = a.meta[j];
+            const float v = Lv(n, j) + Rv(n, j);
+            if (mi >= 0) mo[mi] = v < 0.f ? 1 : 0;
+            if (a.soft) a.soft[frame * N + j] = Lv(n, j);
+        }
+        if (tid == 0) {
+            if (a.iters) a.iters[frame] = it_done;
+            if (a.ok) a.ok[frame] = okv ? 1 : 0;
+        }
+    }
+}
+
+template <int NLOG>
+static int run_alg1_n(const Alg1Args &a, bool scaled, hipStream_t s) {
+    constexpr size_t lds = Alg1Lds<NLOG>::bytes;
+    static_assert(lds <= 160 * 1024, "Algorithm 1 frame exceeds LDS");
+    const int threads = (1 << NLOG) >= 512 ? 256 : ((1 << NLOG) / 2 >= 64 ? (1 << NLOG) / 2 : 64);
+    auto kern = scaled ? k_alg1<NLOG, true> : k_alg1<NLOG, false>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * device_cu_count();
+    if (grid > a.F) grid = a.F;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    e = hipGetLastError();
+    return e == hipSuccess ? PC_OK : hip_fail(e, "Algorithm 1 launch");
+}
+
+__global__ void k_alg1_reset_counter(uint32_t *c) { *c = 0u; }
+
+int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_params &bp,
+                const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
+                hipStream_t s) {
+    const int n = c->n;
+    if (n < 4 || n > 10) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for N = 16 .. 1024");
+    if (bp.stop == PC_STOP_G || (bp.stop == PC_STOP_NONE && c->crc_width == 0))
+        return fail(PC_ENOTSUP, "Algorithm 1 on the GPU checks with the CRC (a code with a CRC, stop none or CRC)");
+    if (pp.P_range < 2 || pp.P_range > n || pp.P_level < 1 || pp.P_level > n - 1 || pp.N_min < 1 || pp.D < 0)
+        return fail(PC_EINVAL, "Algorithm 1 needs 2 <= P_range <= n, 1 <= P_level <= n-1, N_min >= 1, D >= 0");
+    uint32_t *ctr = next_counter(c->device);
+    if (!ctr) return fail(PC_ENOMEM, "queue counter allocation");
+    hipLaunchKernelGGL(k_alg1_reset_counter, dim3(1), dim3(1), 0, s, ctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+    Alg1Args a{};
+    a.llr = d_llr;
+    a.F = F;
+    a.msg = d_msg;
+    a.iters = d_iters;
+    a.ok = d_ok;
+    a.soft = d_soft;
+    a.syn = c->d.syn;
+    a.meta = c->d.meta;
+    a.counter = ctr;
+    a.K_msg = c->K_msg;
+    a.max_iter = bp.max_iter;
+    a.it_min = bp.it_min;
+    a.stop = bp.stop;
+    a.alpha = bp.alpha;
+    a.P_range = pp.P_range;
+    a.P_level = pp.P_level;
+    a.D = pp.D;
+    a.N_min = pp.N_min;
+    a.first_reset = pp.first_reset;
+    a.seed = pp.seed;
+    const bool scaled = bp.alpha != 1.0f;
+    switch (n) {
+        case 4: return run_alg1_n<4>(a, scaled, s);
+        case 5: return run_alg1_n<5>(a, scaled, s);
+        case 6: return run_alg1_n<6>(a, scaled, s);
+        case 7: return run_alg1_n<7>(a, scaled, s);
+        case 8: return run_alg1_n<8>(a, scaled, s);
+        case 9: return run_alg1_n<9>(a, scaled, s);
+        default: return run_alg1_n<10>(a, scaled, s);
+    }
+}
+
+}  // namespace pbp

@@ -304,7 +304,11 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     int kp = 0, T = 1, Q = 1;
     int8_t orders[kMaxPool * kMaxLog] = {0};
     const int n = code->n;
-    if (mode == PC_PP_ALG1) return fail(PC_ENOTSUP, "Algorithm 1 random-subgraph mode is not built for the GPU");
+    if (mode == PC_PP_ALG1) {
+        if (cfg && (cfg->rho || cfg->slots || cfg->grid))
+            return fail(PC_EINVAL, "Algorithm 1 takes no launch shape (one frame per workgroup)");
+        return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, static_cast<hipStream_t>(stream));
+    }
     if (mode != PC_PP_NONE && mode != PC_PP_LASTK && mode != PC_PP_FULL)
         return fail(PC_EINVAL, "unknown multi-trellis mode");
     if (mode == PC_PP_LASTK || mode == PC_PP_FULL) {

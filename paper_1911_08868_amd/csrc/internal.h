@@ -71,6 +71,11 @@ int launch_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_b
 int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
                   hipStream_t stream);
 
+// Algorithm 1 with random subgraphs (per-row stage orders, messages in LDS)
+int launch_alg1(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params &bp,
+                const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
+                hipStream_t stream);
+
 size_t batched_ws_bytes(int64_t F);
 
 size_t wbp_ws_bytes(const pc_code *code, int64_t F, int T);

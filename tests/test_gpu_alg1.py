@@ -1,0 +1,114 @@
+"""GPU parity of Algorithm 1 (random-subgraph partial permutations, Eq. 2
+reset spacing) against the oracle: decided bits, iteration counts, verdicts
+and the u-side L messages (bit-exact; this kernel keeps the sign-magnitude
+check function) on the paper's Table I parameter sets and edge settings."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "published_constants.json")))
+TABLE1 = GOLD["table1_pp_bp_parameters"]
+
+
+@pytest.fixture(scope="module")
+def pbp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1911_08868_amd as m
+    return m
+
+
+def _run(orc, pbp, N, K, cw, poly, F, snr, seed, max_iter, stop, it_min, P_range, P_level, D, N_min,
+         first_reset=0, alpha=1.0, pp_seed=3, dsnr=2.5):
+    import torch
+    oc = orc.construct(N, K, dsnr, cw, poly)
+    msg = synth.message_bits(seed, F, oc.K_msg)
+    _, x = orc.encode(oc, msg)
+    llr = synth.awgn_llr(x, snr, oc.K_msg, seed=seed)
+    code = pbp.Code(N, K, cw, poly, dsnr)
+    bp = pbp.BPParams(max_iter=max_iter, alpha=alpha, stop=stop, it_min=it_min)
+    pp = pbp.PPParams(mode=pbp.PP_ALG1, P_range=P_range, P_level=P_level, D=D, N_min=N_min,
+                      first_reset=first_reset, seed=pp_seed)
+    m, it, ok, soft = pbp.pp_mt_bp_decode(code, torch.from_numpy(llr).cuda(), bp, pp, soft=True)
+    torch.cuda.synchronize()
+    ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=max_iter, alpha=alpha, stop=stop, it_min=it_min,
+                                               pp_mode=orc.PP_ALG1, P_range=P_range, P_level=P_level,
+                                               D=D, N_min=N_min, first_reset=first_reset, seed=pp_seed,
+                                               fp32=True), soft=True, threads=8)
+    return (m.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy(), soft.cpu().numpy()), ref, msg
+
+
+def _assert_parity(got, ref, tag):
+    m, it, ok, soft = got
+    bad = np.nonzero((m != ref.msg_hat).any(1) | (it != ref.iters) | (ok != ref.ok))[0]
+    assert bad.size == 0, f"{tag}: {bad.size} frames differ, first {bad[:5]} iters {it[bad[:5]]} vs {ref.iters[bad[:5]]}"
+    want = ref.soft_u.astype(np.float32)
+    assert np.array_equal(soft.view(np.uint32), want.view(np.uint32)), f"{tag}: soft messages differ"
+
+
+@pytest.mark.parametrize("cw,poly", [(16, 0x1021), (24, 0x1864CFB)])
+def test_table1_n1024_200_iterations(orc, pbp, cw, poly):
+    t = TABLE1["N1024_Nitmax200"]
+    got, ref, msg = _run(orc, pbp, 1024, 512, cw, poly, 48, 1.75, 21, 200, orc.STOP_CRC, 3,
+                         t["P_range"], t["P_level"], t["D"], t["N_min"])
+    _assert_parity(got, ref, f"Table I N=1024 200 it, CRC-{cw}")
+    assert ref.iters.max() > 40  # frames that went through many events
+
+
+def test_table1_n1024_long_budget_parameters(orc, pbp):
+    # the 2e4-iteration parameter set (ranges up to the whole graph) on a
+    # shorter budget
+    t = TABLE1["N1024_Nitmax20000"]
+    got, ref, _ = _run(orc, pbp, 1024, 512, 24, 0x1864CFB, 24, 1.5, 22, 300, orc.STOP_CRC, 3,
+                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+    _assert_parity(got, ref, "Table I N=1024 2e4 set")
+
+
+def test_table1_n512_rate_065(orc, pbp):
+    t = TABLE1["N512_Nitmax20000"]
+    K = int(round(0.65 * 512))
+    got, ref, _ = _run(orc, pbp, 512, K, 24, 0x1864CFB, 40, 2.0, 23, 300, orc.STOP_CRC, 3,
+                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+    _assert_parity(got, ref, "Table I N=512 R=0.65")
+
+
+@pytest.mark.parametrize("N,K,P_range,P_level,D,N_min,first_reset,alpha", [
+    (64, 40, 4, 3, 2, 2, 0, 0.9375),     # scaled min-sum, frequent events
+    (128, 80, 7, 6, 0, 3, 5, 1.0),       # D = 0 (spacing N_min), explicit first event
+    (256, 144, 8, 7, 20, 5, 0, 1.0),
+    (16, 12, 4, 3, 1, 1, 2, 1.0),        # tiny code, every component is small
+])
+def test_alg1_edge_settings(orc, pbp, N, K, P_range, P_level, D, N_min, first_reset, alpha):
+    got, ref, _ = _run(orc, pbp, N, K, 8 if N < 64 else 16, 0x07 if N < 64 else 0x1021, 150, 1.0,
+                       N + P_range, 120, orc.STOP_CRC, 3, P_range, P_level, D, N_min, first_reset, alpha)
+    _assert_parity(got, ref, f"N={N} P_range={P_range} P_level={P_level} D={D}")
+
+
+def test_alg1_no_early_stop(orc, pbp):
+    got, ref, _ = _run(orc, pbp, 256, 128, 16, 0x1021, 40, 2.5, 5, 37, orc.STOP_NONE, 1, 5, 4, 10, 3)
+    _assert_parity(got, ref, "no stop")
+    assert np.all(got[1] == 37)
+
+
+def test_alg1_rejects_what_it_does_not_build(pbp):
+    import torch
+    code = pbp.Code(2048, 1024, 16, 0x1021, 2.5)
+    llr = torch.zeros((2, 2048), dtype=torch.float32, device="cuda")
+    pp = pbp.PPParams(mode=pbp.PP_ALG1, P_range=4, P_level=3, D=4, N_min=2, seed=1)
+    with pytest.raises(pbp.PolarError):
+        pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(max_iter=10, stop=pbp.STOP_CRC), pp)
+    small = pbp.Code(64, 32, 0, 0, 2.0)
+    with pytest.raises(pbp.PolarError):    # G test: not built for Algorithm 1
+        pbp.pp_mt_bp_decode(small, torch.zeros((2, 64), dtype=torch.float32, device="cuda"),
+                            pbp.BPParams(max_iter=10, stop=pbp.STOP_G), pp)
+    code = pbp.Code(256, 144, 16, 0x1021, 2.5)
+    bad = pbp.PPParams(mode=pbp.PP_ALG1, P_range=9, P_level=3, D=4, N_min=2, seed=1)
+    with pytest.raises(pbp.PolarError):    # P_range > n
+        pbp.pp_mt_bp_decode(code, torch.zeros((2, 256), dtype=torch.float32, device="cuda"),
+                            pbp.BPParams(max_iter=10, stop=pbp.STOP_CRC), bad)
