@@ -16,11 +16,22 @@
 // row carries its own order (N x n bytes in LDS) and all L and R levels live
 // in LDS, (2n+1) N floats.
 //
-// Each stage is row-parallel: a thread visits rows tid, tid + blockDim, ...;
-// a row that is the top of its pair for that stage (its pairing bit is 0)
-// computes the processing element (Sec. II-B) and writes both outputs.
-// Stages are separated by workgroup barriers.  The random draws come from a
-// SplitMix64 stream per frame (seed + (frame + 1) * golden ratio, as in the
+// One thread per row (up to 1024 rows).  At each stage a row computes its own
+// output of its processing element (Sec. II-B): with j' the partner of row j,
+// the top row needs f(L_{s-1}[j], L_{s-1}[j'] + R_s[j']) and the bottom row
+// f(R_s[j'], L_{s-1}[j']) + L_{s-1}[j] (L sweep), so both read the same three
+// values and select operands without branching; the R sweep is alike.  The
+// bottom output alone adds a term, which keeps the sign of a zero exactly as
+// the per-pair form gives it.  Consecutive stages need a workgroup barrier
+// only if some row of the reading stage pairs on a bit >= 6, i.e. with a row
+// of another wave; a per-stage flag, recomputed after every event, says so,
+// and the other stages are ordered by the wave's own in-order LDS accesses
+// (in the original graph 6 of n stages pair inside a wave).  Overwrites of
+// values other waves read are ordered by the barriers of the decision (L
+// sweep reads, R levels) and by one barrier after the R sweep (its reads of
+// L levels, rewritten by the next L sweep).  The order table
+// is stage-major, [n][N], so a stage's reads are consecutive bytes.  The
+// random draws come from a SplitMix64 stream per frame (seed + (frame + 1) * golden ratio, as in the
 // CPU reference decoder) that every thread advances identically, so all
 // control decisions are uniform.  The component labels of stages 1..m are
 // found by propagating the smallest row index over the pairs until nothing
@@ -67,19 +78,22 @@ struct Alg1Lds {
     static constexpr size_t msg_floats = (size_t)(2 * n + 1) * N;  // L levels 0..n, R levels 1..n
     static constexpr size_t ord_bytes = ((size_t)N * n + 15) & ~(size_t)15;
     static constexpr size_t bytes = msg_floats * 4 + ord_bytes + (size_t)N * 4 + 64 * 4;
+    static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
 template <int NLOG, bool SCALED>
-__global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
+__global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
     constexpr int N = 1 << NLOG, n = NLOG;
     using Lay = Alg1Lds<NLOG>;
     const int tid = threadIdx.x, nt = blockDim.x;
     extern __shared__ __align__(16) float smem[];
     float *const Lm = smem;                  // level l at Lm + l N, l = 0..n
     float *const Rm = smem + (size_t)(n + 1) * N - N;  // level l at Rm + l N, l = 1..n
-    int8_t *const ord = reinterpret_cast<int8_t *>(smem + Lay::msg_floats);  // [N][n]
+    int8_t *const ord = reinterpret_cast<int8_t *>(smem + Lay::msg_floats);  // [n][N]: bit of stage s of row j at (s-1) N + j
     int32_t *const lab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ord) + Lay::ord_bytes);
-    int32_t *const misc = lab + N;           // [0] frame, [1] flag, [2] count, [3] root, [4..] wave partials
+    // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
+    // counts, [40 + s] stage s pairs across waves
+    int32_t *const misc = lab + N;
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
     auto Lv = [&](int l, int j) -> float & { return Lm[(size_t)l * N + j]; };
@@ -94,6 +108,15 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
         __syncthreads();
         return misc[1] != 0;
     };
+    // per-wave population counts of a predicate, published in misc[20 + w]
+    const int wave = tid >> 6, nwaves = (nt + 63) >> 6, lane = tid & 63;
+    auto wave_counts = [&](bool v) -> uint64_t {
+        const uint64_t mask = __ballot(v);
+        __syncthreads();
+        if (lane == 0) misc[20 + wave] = __popcll(mask);
+        __syncthreads();
+        return mask;
+    };
     auto wg_xor = [&](uint32_t v) -> uint32_t {
         v = lanes_xor<64>(v);
         __syncthreads();
@@ -102,6 +125,38 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
         uint32_t s = 0;
         for (int w = 0; w < (nt + 63) / 64; ++w) s ^= (uint32_t)misc[4 + w];
         return s;
+    };
+
+    // stage s pairs some row with a row of another wave (bit >= 6)
+    auto update_cross = [&](bool row, int j) {
+        __syncthreads();
+        if (tid < n) misc[41 + tid] = 0;
+        __syncthreads();
+        if (row)
+            for (int s = 1; s <= n; ++s)
+                if (ord[(s - 1) * N + j] >= 6) misc[40 + s] = 1;
+        __syncthreads();
+    };
+    // the thread's partner (byte offset) and top flag at every stage, cached
+    // in registers between events
+    int pofs[n];
+    uint32_t topm = 0;
+    auto load_pairs = [&](bool row, int j) {
+        topm = 0;
+        sfor<0, n>([&](auto s0) {
+            const int b = row ? ord[s0 * N + j] : 0;
+            pofs[s0] = 4 * (j ^ (1 << b));
+            topm |= (((j >> b) & 1) == 0 ? 1u : 0u) << s0;
+        });
+    };
+    auto stage_sync = [&](int s) {
+        if (misc[40 + s]) {
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     };
 
     for (;;) {
@@ -113,12 +168,14 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
 
         // ---- initialise L and R (Alg. 1 initializeLandR) and the orders ----
         const float *src = a.llr + frame * N;
-        for (int j = tid; j < N; j += nt) {
+        const int j = tid;
+        const bool row = j < N;
+        if (row) {
             Lv(0, j) = src[j];
             for (int l = 1; l <= n; ++l) Lv(l, j) = 0.f;
             for (int l = 1; l < n; ++l) Rv(l, j) = 0.f;
             Rv(n, j) = a.meta[j] == -2 ? inf : 0.f;
-            for (int s = 0; s < n; ++s) ord[j * n + s] = (int8_t)s;
+            for (int s = 0; s < n; ++s) ord[s * N + j] = (int8_t)s;
         }
         uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
         int next_reset;
@@ -129,29 +186,29 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
             const int v = full > a.N_min ? full : a.N_min;
             next_reset = v < a.max_iter / 2 ? v : a.max_iter / 2;
         }
-        __syncthreads();
+        update_cross(row, j);
+        load_pairs(row, j);
 
         int it_done = a.max_iter;
         bool okv = false;
         for (int it = 1; it <= a.max_iter; ++it) {
             // ---- L sweep, stages 1..n ----
-            for (int s = 1; s <= n; ++s) {
-                for (int j = tid; j < N; j += nt) {
-                    const int b = ord[j * n + s - 1];
-                    if ((j >> b) & 1) continue;
-                    const int jp = j | (1 << b);
-                    const float l1 = Lv(s - 1, j), l2 = Lv(s - 1, jp), r1 = Rv(s, j), r2 = Rv(s, jp);
-                    Lv(s, j) = cnode<SCALED>(l1, l2 + r2, alpha);
-                    Lv(s, jp) = cnode<SCALED>(r1, l1, alpha) + l2;
+            sfor<1, n + 1>([&](auto sc) {
+                constexpr int s = sc;
+                stage_sync(s);  // level s-1 and R_s of the partner rows
+                if (row) {
+                    const bool top = (topm >> (s - 1)) & 1u;
+                    const float A = Lv(s - 1, j);
+                    const float B = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
+                    const float C = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
+                    // top: f(L[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + L[j]
+                    const float c = cnode<SCALED>(top ? A : C, top ? B + C : B, alpha);
+                    Lv(s, j) = top ? c : c + A;
                 }
-                __syncthreads();
-            }
+            });
             // ---- decision and CRC syndrome on level n+1 ----
             uint32_t syn = 0;
-            for (int j = tid; j < N; j += nt) {
-                const float v = Lv(n, j) + Rv(n, j);
-                if (v < 0.f) syn ^= a.syn[j];
-            }
+            if (row && Lv(n, j) + Rv(n, j) < 0.f) syn = a.syn[j];
             const bool pass = wg_xor(syn) == 0u;
             if (a.stop == PC_STOP_CRC && it >= a.it_min && pass) {
                 it_done = it;
@@ -163,17 +220,22 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
                 break;
             }
             // ---- R sweep, stages n..2 (R on the channel level is never read) ----
-            for (int s = n; s >= 2; --s) {
-                for (int j = tid; j < N; j += nt) {
-                    const int b = ord[j * n + s - 1];
-                    if ((j >> b) & 1) continue;
-                    const int jp = j | (1 << b);
-                    const float l1 = Lv(s - 1, j), l2 = Lv(s - 1, jp), r1 = Rv(s, j), r2 = Rv(s, jp);
-                    Rv(s - 1, j) = cnode<SCALED>(r1, l2 + r2, alpha);
-                    Rv(s - 1, jp) = cnode<SCALED>(r1, l1, alpha) + r2;
+            sfor<0, n - 1>([&](auto kc) {
+                constexpr int s = n - kc;
+                stage_sync(s);  // R_s and level s-1 of the partner rows
+                if (row) {
+                    const bool top = (topm >> (s - 1)) & 1u;
+                    const float P = Rv(s, j);
+                    const float Q = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
+                    const float S = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
+                    // top: f(R[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + R[j]
+                    const float c = cnode<SCALED>(top ? P : S, top ? Q + S : Q, alpha);
+                    Rv(s - 1, j) = top ? c : c + P;
                 }
-                __syncthreads();
-            }
+            });
+            // the R sweep read partners' L messages, which the next L sweep
+            // overwrites; the decision's barriers order the other hazards
+            __syncthreads();
             // ---- partial permutation of one subgraph (Alg. 1 partialPermute) ----
             if (it == next_reset) {
                 int n_zero = 0;
@@ -185,16 +247,15 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
                     const int nblocks = N >> m;
                     const int blk = (int)draw_below(st, (uint32_t)nblocks);
                     // components of stages 1..m: smallest row index by propagation
-                    for (int j = tid; j < N; j += nt) lab[j] = j;
+                    if (row) lab[j] = j;
                     bool changed = true;
                     while (changed) {
                         bool c = false;
                         __syncthreads();
-                        for (int j = tid; j < N; j += nt) {
+                        if (row) {
                             int v = lab[j];
                             for (int s = 1; s <= m; ++s) {
-                                const int p = j ^ (1 << ord[j * n + s - 1]);
-                                const int w = lab[p];
+                                const int w = lab[j ^ (1 << ord[(s - 1) * N + j])];
                                 v = w < v ? w : v;
                             }
                             if (v < lab[j]) {
@@ -204,39 +265,31 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
                         }
                         changed = wg_or(c);
                     }
-                    // number of components and the root of rank blk
-                    __syncthreads();
-                    if (tid == 0) {
-                        int cnt = 0, root = -1;
-                        for (int j = 0; j < N; ++j) {
-                            if (lab[j] == j) {
-                                if (cnt == blk) root = j;
-                                ++cnt;
-                            }
-                        }
-                        misc[2] = cnt;
-                        misc[3] = root;
+                    // components (their smallest rows) and the one of rank blk
+                    const bool is_root = row && lab[j] == j;
+                    const uint64_t rmask = wave_counts(is_root);
+                    int before = 0, total = 0;
+                    for (int w = 0; w < nwaves; ++w) {
+                        total += misc[20 + w];
+                        if (w < wave) before += misc[20 + w];
                     }
+                    if (total != nblocks) continue;
+                    if (is_root && before + __popcll(rmask & ((1ull << lane) - 1)) == blk) misc[3] = j;
                     __syncthreads();
-                    if (misc[2] != nblocks) continue;
                     const int root = misc[3];
                     // size of the block and one bit per permuted stage over it
-                    int members = 0;
+                    const bool member = row && lab[j] == root;
                     bool mixed = false;
-                    for (int j = tid; j < N; j += nt) {
-                        if (lab[j] != root) continue;
-                        ++members;
-                        for (int s = rl; s <= m; ++s) mixed |= ord[j * n + s - 1] != ord[root * n + s - 1];
-                    }
-                    __syncthreads();
-                    if (tid == 0) misc[2] = 0;
-                    __syncthreads();
-                    if (members) atomicAdd(&misc[2], members);
+                    if (member)
+                        for (int s = rl; s <= m; ++s) mixed |= ord[(s - 1) * N + j] != ord[(s - 1) * N + root];
+                    wave_counts(member);
+                    int members = 0;
+                    for (int w = 0; w < nwaves; ++w) members += misc[20 + w];
                     const bool bad = wg_or(mixed);
-                    if (bad || misc[2] != (1 << m)) continue;
+                    if (bad || members != (1 << m)) continue;
                     // a new non-identity order of the bits of stages rl..m
                     int8_t bits[kMaxLog], cand[kMaxLog];
-                    for (int i = 0; i < rr; ++i) bits[i] = ord[root * n + rl - 1 + i];
+                    for (int i = 0; i < rr; ++i) bits[i] = ord[(rl - 1 + i) * N + root];
                     bool ident = true;
                     while (ident) {
                         for (int i = 0; i < rr; ++i) cand[i] = bits[i];
@@ -250,9 +303,8 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
                         for (int i = 0; i < rr; ++i) ident &= cand[i] == bits[i];
                     }
                     __syncthreads();  // every thread has read the old orders of the root
-                    for (int j = tid; j < N; j += nt) {
-                        if (lab[j] != root) continue;
-                        for (int i = 0; i < rr; ++i) ord[j * n + rl - 1 + i] = cand[i];
+                    if (member) {
+                        for (int i = 0; i < rr; ++i) ord[(rl - 1 + i) * N + j] = cand[i];
                         // levels strictly between the permuted stages (Sec. III)
                         for (int l = rl; l <= m - 1; ++l) {
                             Lv(l, j) = 0.f;
@@ -265,13 +317,14 @@ __global__ void __launch_bounds__(256) k_alg1(Alg1Args a) {
                 int add = a.D > 0 ? n_zero / a.D : 0;
                 if (add < a.N_min) add = a.N_min;
                 next_reset = it + add;
-                __syncthreads();
+                update_cross(row, j);
+                load_pairs(row, j);
             }
         }
 
         // ---- outputs (Alg. 1 hardDecision) ----
         uint8_t *mo = a.msg + frame * a.K_msg;
-        for (int j = tid; j < N; j += nt) {
+        if (row) {
             const int mi = a.meta[j];
             const float v = Lv(n, j) + Rv(n, j);
             if (mi >= 0) mo[mi] = v < 0.f ? 1 : 0;
@@ -288,7 +341,7 @@ template <int NLOG>
 static int run_alg1_n(const Alg1Args &a, bool scaled, hipStream_t s) {
     constexpr size_t lds = Alg1Lds<NLOG>::bytes;
     static_assert(lds <= 160 * 1024, "Algorithm 1 frame exceeds LDS");
-    const int threads = (1 << NLOG) >= 512 ? 256 : ((1 << NLOG) / 2 >= 64 ? (1 << NLOG) / 2 : 64);
+    const int threads = Alg1Lds<NLOG>::threads;
     auto kern = scaled ? k_alg1<NLOG, true> : k_alg1<NLOG, false>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);

@@ -11,6 +11,9 @@ weighted_bp_large(): the same at N=4096 with the last-5 trellis schedule and
 
 batched_mixed(): the mixed-length stream through the persistent queue kernel
 (see batched.py).
+
+alg1_table1(): Algorithm 1 with random subgraphs (Table I parameters) beside
+the fixed last-k schedule.
 """
 from __future__ import annotations
 
@@ -180,11 +183,48 @@ def weighted_bp_large(torch, pbp, F_train=1024, F_dec=8192, T=20, steps=2, warmu
             "avg_iters_unit": round(outs[1].double().mean().item(), 3)}
 
 
+def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
+    """Algorithm 1 with random subgraphs (Table I, N_it,max = 200: P_range 2,
+    P_level 6, D 8, N_min 4) at N=1024, R=1/2 (K=512 with CRC-24), beside
+    the fixed last-4 schedule on the same frames."""
+    import synth
+    code = pbp.Code(1024, 512, 24, 0x1864CFB, 2.5)
+    bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
+    alg1 = pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)
+    lastk = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
+    points = []
+    for snr in snrs:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(snr * 100))
+        m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+        x = pbp.encode(code, m)
+        llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
+                                   code.K_msg, gen)
+        row = {"ebn0_db": snr}
+        for name, pp in (("alg1", alg1), ("lastk4", lastk)):
+            out = pbp.pp_mt_bp_decode(code, llr, bp, pp)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            out = pbp.pp_mt_bp_decode(code, llr, bp, pp, out=out[:3])
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            row[name] = {"gbit_s": round(F * code.K_msg / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
+                         "avg_iters": round(out[1].double().mean().item(), 3),
+                         "fer": (out[0] != m).any(1).double().mean().item()}
+        points.append(row)
+        _log(f"Algorithm 1 at {snr} dB: {row['alg1']['ms']} ms vs last-4 {row['lastk4']['ms']} ms")
+    return {"workload": f"Algorithm 1 (Table I, 200-iteration set: P_range 2, P_level 6, D 8, N_min 4) vs "
+                        f"fixed last-4 schedule, N=1024 K=512 incl. CRC-24, {F} frames per Eb/N0 point, "
+                        f"max 200 iterations, CRC stop", "points": points}
+
+
 def bench_extras(torch, pbp):
     from .batched import bench_mixed
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
-                     ("batched_mixed", bench_mixed)):
+                     ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1)):
         try:
             out[name] = fn(torch, pbp)
         except Exception as e:  # report the failure in the JSON line, keep the rest
