@@ -170,11 +170,14 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         const float *src = a.llr + frame * N;
         const int j = tid;
         const bool row = j < N;
+        // the thread's own row on every level, mirrored in registers
+        float Lown[n + 1], Rown[n + 1];
+        sfor<0, n + 1>([&](auto l) { Lown[l] = 0.f; Rown[l] = 0.f; });
         if (row) {
-            Lv(0, j) = src[j];
-            for (int l = 1; l <= n; ++l) Lv(l, j) = 0.f;
-            for (int l = 1; l < n; ++l) Rv(l, j) = 0.f;
-            Rv(n, j) = a.meta[j] == -2 ? inf : 0.f;
+            Lown[0] = src[j];
+            Rown[n] = a.meta[j] == -2 ? inf : 0.f;
+            sfor<0, n + 1>([&](auto l) { Lv(l, j) = Lown[l]; });
+            sfor<1, n + 1>([&](auto l) { Rv(l, j) = Rown[l]; });
             for (int s = 0; s < n; ++s) ord[s * N + j] = (int8_t)s;
         }
         uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
@@ -198,17 +201,18 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 stage_sync(s);  // level s-1 and R_s of the partner rows
                 if (row) {
                     const bool top = (topm >> (s - 1)) & 1u;
-                    const float A = Lv(s - 1, j);
+                    const float A = Lown[s - 1];
                     const float B = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
                     const float C = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
                     // top: f(L[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + L[j]
                     const float c = cnode<SCALED>(top ? A : C, top ? B + C : B, alpha);
-                    Lv(s, j) = top ? c : c + A;
+                    Lown[s] = top ? c : c + A;
+                    Lv(s, j) = Lown[s];
                 }
             });
             // ---- decision and CRC syndrome on level n+1 ----
             uint32_t syn = 0;
-            if (row && Lv(n, j) + Rv(n, j) < 0.f) syn = a.syn[j];
+            if (row && Lown[n] + Rown[n] < 0.f) syn = a.syn[j];
             const bool pass = wg_xor(syn) == 0u;
             if (a.stop == PC_STOP_CRC && it >= a.it_min && pass) {
                 it_done = it;
@@ -225,12 +229,13 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 stage_sync(s);  // R_s and level s-1 of the partner rows
                 if (row) {
                     const bool top = (topm >> (s - 1)) & 1u;
-                    const float P = Rv(s, j);
+                    const float P = Rown[s];
                     const float Q = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
                     const float S = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
                     // top: f(R[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + R[j]
                     const float c = cnode<SCALED>(top ? P : S, top ? Q + S : Q, alpha);
-                    Rv(s - 1, j) = top ? c : c + P;
+                    Rown[s - 1] = top ? c : c + P;
+                    Rv(s - 1, j) = Rown[s - 1];
                 }
             });
             // the R sweep read partners' L messages, which the next L sweep
@@ -306,10 +311,14 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                     if (member) {
                         for (int i = 0; i < rr; ++i) ord[(rl - 1 + i) * N + j] = cand[i];
                         // levels strictly between the permuted stages (Sec. III)
-                        for (int l = rl; l <= m - 1; ++l) {
-                            Lv(l, j) = 0.f;
-                            Rv(l, j) = 0.f;
-                        }
+                        sfor<1, n>([&](auto l) {
+                            if (l >= rl && l <= m - 1) {
+                                Lown[l] = 0.f;
+                                Rown[l] = 0.f;
+                                Lv(l, j) = 0.f;
+                                Rv(l, j) = 0.f;
+                            }
+                        });
                     }
                     n_zero = (1 << m) * (rr - 1);
                     break;
@@ -326,9 +335,9 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         uint8_t *mo = a.msg + frame * a.K_msg;
         if (row) {
             const int mi = a.meta[j];
-            const float v = Lv(n, j) + Rv(n, j);
+            const float v = Lown[n] + Rown[n];
             if (mi >= 0) mo[mi] = v < 0.f ? 1 : 0;
-            if (a.soft) a.soft[frame * N + j] = Lv(n, j);
+            if (a.soft) a.soft[frame * N + j] = Lown[n];
         }
         if (tid == 0) {
             if (a.iters) a.iters[frame] = it_done;
