@@ -161,6 +161,16 @@ def bench_mixed(torch, pbp, frames_total=4_000_000, rounds=4, cfg=None):
     bits = sum(int(d.Kmsg[d.code_id.to(torch.int64)].sum().item()) for d in decs)
     errs = sum(frame_errors(torch, d, g) for d, g in zip(decs, groups))
     iters = torch.cat([d.iters for d in decs]).double()
+    # algorithmic VALU lane-ops as for the single-length decoder: 6 per
+    # processing element, N/2 per stage, n stages per L sweep and n-1 live
+    # stages per R sweep (the deciding iteration runs no R sweep)
+    ops = 0.0
+    for d in decs:
+        Nf = d.N[d.code_id.to(torch.int64)].double()
+        nf = torch.log2(Nf)
+        it = d.iters.double()
+        ops += (3 * Nf * (nf * it + (nf - 1) * (it - 1))).sum().item()
+    alu_peak = 256 * 64 * 2.4e9
     _log(f"mixed stream: {ms:.1f} ms")
     out = {"workload": f"{frames_total} frames, N ~ U{{128,256,512,1024}}, R ~ U{{1/4,1/3,1/2,2/3,3/4}}, "
                        "CRC-16, Eb/N0 ~ U[1,4] dB, PP-MT-BP k=4 T=10 Q=8, max 200 iterations, "
@@ -168,6 +178,7 @@ def bench_mixed(torch, pbp, frames_total=4_000_000, rounds=4, cfg=None):
            "gbit_s": round(bits / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
            "frames_s": round(frames_total / (ms / 1e3), 1),
            "avg_iters": round(iters.mean().item(), 3), "fer": errs / frames_total,
+           "alu_frac": round(ops / (ms / 1e3) / alu_peak, 4),
            "launch": {"rho": cfg.rho, "slots": cfg.slots}}
     del decs
     torch.cuda.empty_cache()

@@ -118,7 +118,12 @@ __device__ __forceinline__ void run_bucket(const BatchedArgs &a, float *smem) {
     const int S = blockDim.x / TPS;
     BatchSrc<(1 << NLOG)> src(a, NLOG - 6);
     DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, a.orders[NLOG - 6]};
-    decode_loop<NLOG, KP, RHO, SCALED, false>(src, c, smem, S);
+    // The thread index goes through an empty asm so that nothing derived
+    // from it is shared with (and kept live across) the other lengths'
+    // loops: each loop alone fits 128 VGPRs, all five together spilled.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    decode_loop<NLOG, KP, RHO, SCALED, false>(src, c, smem, S, tid);
 }
 
 template <int KPQ, int RHO, bool SCALED>

@@ -274,6 +274,20 @@ __device__ __forceinline__ float byte_at(const float *p, int byte_off) {
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + byte_off);
 }
 
+// Synchronisation at a group boundary: a workgroup barrier, or, where the
+// exchange stays inside each wave, only a compiler barrier that keeps the
+// LDS stores before the loads.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void boundary_sync() {
+    if constexpr (WAVE_LOCAL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // relabelled row p -> original row for stage order e[0..n-1]: bit s of p is
 // bit e[s] of the original row.  Only bits lowbits..n-1 can move.
 __device__ __forceinline__ int relabel_to_row(int p, const int8_t *e, int n, int lowbits) {

@@ -63,20 +63,6 @@ constexpr int decode_min_waves() {
     return RHO <= 2 ? 4 : 2;
 }
 
-// Synchronisation at a group boundary: a workgroup barrier, or, where the
-// exchange stays inside each wave, only a compiler barrier that keeps the
-// LDS stores before the loads.
-template <bool WAVE_LOCAL>
-__device__ __forceinline__ void boundary_sync() {
-    if constexpr (WAVE_LOCAL) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
 // Iteration parameters shared by every frame source.
 struct DecodeCtl {
     int32_t max_iter, it_min, stop;
@@ -88,8 +74,10 @@ struct DecodeCtl {
 // The lock-step slot loop.  Src supplies frames: pop() (slot leader only)
 // returns the next frame or a value >= Src::F when the queue is empty;
 // per frame it gives the LLR pointer, the code tables and the output sinks.
+// tid is the thread's index in the workgroup (threadIdx.x, or a copy the
+// caller has hidden from the optimiser).
 template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, class Src>
-__device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float *smem, int S) {
+__device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float *smem, int S, const int tid) {
     using P = Plan<NLOG, KP, RHO>;
     constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG;
     constexpr int GB = P::GB;
@@ -98,7 +86,6 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     constexpr bool MAPPED_BOUNDARY = (KP > 0 && KP < NLOG);
     constexpr int LOWBITS = NLOG - KP;
 
-    const int tid = threadIdx.x;
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
     const int F = (int)src.F;
@@ -424,7 +411,7 @@ k_decode(DecodeArgs a) {
     const int S = blockDim.x / TPS;
     DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0]};
     SingleSrc<(1 << NLOG)> src(a);
-    decode_loop<NLOG, KP, RHO, SCALED, GMODE>(src, c, smem, S);
+    decode_loop<NLOG, KP, RHO, SCALED, GMODE>(src, c, smem, S, (int)threadIdx.x);
 }
 
 }  // namespace pbp

@@ -57,10 +57,22 @@ __device__ __forceinline__ float sgnf(float v) { return (__float_as_uint(v) >> 3
 // handoffs (every phase ends at a barrier), plus a ping-pong pair of
 // weight-gradient staging buffers of RHO N floats each, one per reverse step.
 // The pool orders follow the slots.
+// A frame of at most one wave (TPS <= 64) exchanges group boundaries only
+// inside its wave: its kernels take no workgroup barrier per group step, and
+// the adjoint stages a whole iteration's weight gradients per frame (2 n N
+// floats) so that the sum over the workgroup's frames needs one barrier per
+// iteration instead of one per step.
+template <class P>
+constexpr bool wbp_wave_frame() { return P::TPS <= 64; }
+
 template <class P, bool BWD>
 struct WbpLds {
-    static constexpr size_t per_slot = (size_t)(BWD ? 4 + 2 * P::rho : 4) * P::N * sizeof(float);
-    static constexpr size_t bytes(int S) { return (size_t)S * per_slot + 8 * 16; }
+    static constexpr size_t per_slot =
+        (size_t)(BWD ? 4 + (wbp_wave_frame<P>() ? 2 * P::n : 2 * P::rho) : 4) * P::N * sizeof(float);
+    // the forward keeps the pool orders in LDS after the slots; the adjoint
+    // reads them from its arguments (at N = 256 its four slots take exactly
+    // half of the LDS, so two workgroups share a CU)
+    static constexpr size_t bytes(int S) { return (size_t)S * per_slot + (BWD ? 0 : 8 * 16); }
 };
 
 template <int NLOG, int RHO>
@@ -280,6 +292,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
     constexpr bool MAPPED = (KP > 0 && KP < NLOG);
     constexpr int LOWBITS = NLOG - KP;
     constexpr int NREG = RState<P>::NREG;
+    constexpr bool WAVE = wbp_wave_frame<P>();
     const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
     const int64_t frame = (int64_t)blockIdx.x * S + slot;
     const bool active = frame < a.F;
@@ -354,7 +367,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                 float *lt = buf + ((g + 1) & 1) * N;
                 sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
             }
-            __syncthreads();
+            boundary_sync<WAVE>();
         });
         if (active) {
             if constexpr (G > 1) {
@@ -381,7 +394,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                 }
             }
         }
-        __syncthreads();
+        boundary_sync<WAVE>();
         if (it == a.T - 1) break;
         sfor<0, G - 1>([&](auto k) {
             constexpr int g = G - 2 - k;
@@ -397,7 +410,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                     else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
                 }
             }
-            __syncthreads();
+            boundary_sync<WAVE>();
         });
     }
 }
@@ -410,18 +423,19 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     constexpr int LOWBITS = NLOG - KP;
     constexpr int NREG = RState<P>::NREG;
     constexpr int RI = P::RI;
+    constexpr bool WAVE = wbp_wave_frame<P>();
     const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
     const int64_t frame0 = (int64_t)blockIdx.x * S, frame = frame0 + slot;
     const bool active = frame < a.F;
     constexpr size_t PS = WbpLds<P, true>::per_slot / sizeof(float);
     extern __shared__ __align__(16) float smem[];
-    // [A0 A1 | B0 B1 | W0 W1]: L and R boundary pairs of the recomputed
-    // sweeps; the reverse R sweep passes adjoints through A, the reverse L
-    // sweep through B; W holds the weight gradients of one reverse step
+    // [A0 A1 | B0 B1 | W]: L and R boundary pairs of the recomputed sweeps;
+    // the reverse R sweep passes adjoints through A, the reverse L sweep
+    // through B; W holds the weight gradients of one reverse step (W0 W1,
+    // RHO N floats each) or, for a one-wave frame, of the whole iteration
+    // ([n][2][N])
     float *const buf = smem + (size_t)slot * PS;
-    int8_t *const ords = reinterpret_cast<int8_t *>(smem + (size_t)S * PS);
-    for (int i = tid; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i >> 4][i & 15];
-    __syncthreads();
+    const int8_t *const ords = &a.orders[0][0];
 
     Regs<P> st;                         // entering R state and this iteration's L messages
     float Rsw[G][RI][ROWS], Rtsw[G][ROWS];  // R messages of this iteration's R sweep
@@ -437,6 +451,18 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     // Sum the weight gradients that one reverse step (group g, sweep d)
     // staged in W[par] over the workgroup's frames, in slot order, and store
     // them as this workgroup's partial of iteration it.
+    // one-wave frames: sum the iteration's staged gradients over the
+    // workgroup's frames, in slot order (the last iteration's R weights get 0)
+    auto flush_all = [&](int it, bool lastit) {
+        float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+        for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
+            float v = 0.f;
+            if (!(lastit && ((idx / N) & 1)))
+                for (int s = 0; s < S; ++s)
+                    if (frame0 + s < a.F) v += smem[(size_t)s * PS + 4 * N + idx];
+            part[idx] = v;
+        }
+    };
     auto flush = [&](auto gc, int d, int par, int it) {
         constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
         float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N + lo * 2 * N;
@@ -510,7 +536,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                 float *lt = buf + ((g + 1) & 1) * N;
                 sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
             }
-            __syncthreads();
+            boundary_sync<WAVE>();
         });
         float prior[ROWS];
         sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
@@ -534,7 +560,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                 }
             }
         }
-        __syncthreads();
+        boundary_sync<WAVE>();
         if (!lastit) {
             sfor<0, G - 1>([&](auto k) {
                 constexpr int g = G - 2 - k;
@@ -550,11 +576,11 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                         else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
                     }
                 }
-                __syncthreads();
+                boundary_sync<WAVE>();
             });
             // ---- reverse of the R sweep: groups bottom to top ----
             sfor<0, G>([&](auto g) {
-                if constexpr (g > 0) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
+                if constexpr (g > 0 && !WAVE) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
                 if (active) {
                     const int base = GMap<P, g>::base(t);
                     float gb[ROWS];
@@ -566,15 +592,18 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                         else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
                     }
                     float gtop[ROWS];
-                    float *const gws = buf + 4 * N + (g & 1) * RHO * N + base;
+                    // staged at [sl][row] of this step, or at [stage][1][row] for one-wave frames
+                    float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2 + 1) * N + base
+                                            : buf + 4 * N + (g & 1) * RHO * N + base;
+                    constexpr int SLS = WAVE ? 2 * N : N;
                     rev_group_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                      wt + base, [&](int sl, int off, float v) { gws[sl * N + off] = v; });
+                                      wt + base, [&](int sl, int off, float v) { gws[sl * SLS + off] = v; });
                     if constexpr (g < G - 1) {
                         float *dst = buf + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
                     }
                 }
-                __syncthreads();
+                boundary_sync<WAVE>();
             });
         }
         // the new state adjoint comes only from the reverse L sweep
@@ -586,12 +615,15 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
         const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
         sfor<0, G>([&](auto k) {
             constexpr int g = G - 1 - k;
-            if constexpr (k == 0) {
-                if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
-            } else {
-                flush(std::integral_constant<int, g + 1>{}, 0, (step0 + k - 1) & 1, it);
+            if constexpr (!WAVE) {
+                if constexpr (k == 0) {
+                    if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
+                } else {
+                    flush(std::integral_constant<int, g + 1>{}, 0, (step0 + k - 1) & 1, it);
+                }
             }
-            float *const gws = buf + 4 * N + ((step0 + k) & 1) * RHO * N;
+            float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2) * N : buf + 4 * N + ((step0 + k) & 1) * RHO * N;
+            constexpr int SLS = WAVE ? 2 * N : N;
             if (active) {
                 const int base = GMap<P, g>::base(t);
                 float gt[ROWS];
@@ -599,12 +631,12 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                     if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
                     else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
                     rev_group_L<P, g, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g], gsi[g],
-                                            gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * N + base + off] = v; });
+                                            gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; });
                 } else {
                     const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
                     rev_group_L<P, g, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g], glb[g],
-                                             gsi[g], gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * N + base + off] = v; });
+                                             gsi[g], gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; });
                 }
                 if constexpr (g > 0) {
                     float *dst = buf + 2 * N + (g & 1) * N;
@@ -612,13 +644,18 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
                     else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[g][i]; });
                 }
             }
-            __syncthreads();
+            boundary_sync<WAVE>();
         });
-        flush(std::integral_constant<int, 0>{}, 0, (step0 + G - 1) & 1, it);
-        if (lastit) {
-            // the last iteration runs no R sweep: its R weights get no gradient
-            float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
-            for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
+        if constexpr (WAVE) {
+            __syncthreads();
+            flush_all(it, lastit);
+        } else {
+            flush(std::integral_constant<int, 0>{}, 0, (step0 + G - 1) & 1, it);
+            if (lastit) {
+                // the last iteration runs no R sweep: its R weights get no gradient
+                float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+                for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
+            }
         }
         __syncthreads();
     }
