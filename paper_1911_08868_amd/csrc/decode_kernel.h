@@ -85,6 +85,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     constexpr int WPS = P::WPS;
     constexpr bool MAPPED_BOUNDARY = (KP > 0 && KP < NLOG);
     constexpr int LOWBITS = NLOG - KP;
+    // A frame of at most one wave (TPS <= 64) exchanges nothing with other
+    // waves: each wave then runs its slots on its own, with no workgroup
+    // barrier in the loop (refill, syndrome and G test stay inside the wave)
+    // and leaves when none of its slots has a frame.
+    constexpr bool WSLOT = TPS <= 64;
 
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
@@ -103,12 +108,14 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     if constexpr (GMODE) {
         for (int w = tid; w < S * 2 * NW; w += blockDim.x) gwords[w] = 0u;
     }
+    if constexpr (WSLOT) __syncthreads();  // the orders and words before any wave starts
 
     Regs<P> st;
     uint32_t synv[ROWS];
     float prior[ROWS];  // R on level n+1 of this thread's rows: +inf frozen, 0 information
     int baddr[ROWS];  // byte offsets of the relabelled boundary rows
     uint32_t ubits = 0;
+    uint32_t synv_total = 0;  // the slot's syndrome (one-wave frames)
     int it = 0, q = 0, next_ev = 0;
     int frame = 0;  // frame indices fit 31 bits (the host checks F)
     const uint32_t *tsyn = nullptr;
@@ -176,23 +183,36 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
     for (;;) {
         // ---- queue: refill finished slots --------------------------------
-        // one frame per workgroup (S == 1): need_new is uniform, so the queue
-        // round trip and its barrier happen only when the frame ends
-        const bool refill = S > 1 || need_new;
-        if (refill) {
-            if (need_new && t == 0) frame_slot[slot] = (int)src.pop();
-            __syncthreads();
-        }
-        if (need_new) {
-            frame = frame_slot[slot];
-            active = frame < F;
-            need_new = false;
-            if (active) start_frame();
-        }
-        if (refill) {
-            bool any = false;
-            for (int s = 0; s < S; ++s) any |= frame_slot[s] < F;
-            if (!any) break;
+        if constexpr (WSLOT) {
+            // the slot's leader pops; its lanes read the frame after a wave fence
+            if (need_new) {
+                if (t == 0) frame_slot[slot] = (int)src.pop();
+                boundary_sync<true>();
+                frame = frame_slot[slot];
+                active = frame < F;
+                need_new = false;
+                if (active) start_frame();
+            }
+            if (__ballot(active) == 0ull) break;
+        } else {
+            // one frame per workgroup (S == 1): need_new is uniform, so the queue
+            // round trip and its barrier happen only when the frame ends
+            const bool refill = S > 1 || need_new;
+            if (refill) {
+                if (need_new && t == 0) frame_slot[slot] = (int)src.pop();
+                __syncthreads();
+            }
+            if (need_new) {
+                frame = frame_slot[slot];
+                active = frame < F;
+                need_new = false;
+                if (active) start_frame();
+            }
+            if (refill) {
+                bool any = false;
+                for (int s = 0; s < S; ++s) any |= frame_slot[s] < F;
+                if (!any) break;
+            }
         }
 
         // ---- L sweep: groups 0..G-2 ---------------------------------------
@@ -251,7 +271,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             }
             if constexpr (!GMODE) {
                 syn = lanes_xor<(TPS < 64 ? TPS : 64)>(syn);
-                if ((t & 63) == 0) synpart[slot * WPS + (t >> 6)] = syn;
+                if constexpr (WSLOT) {
+                    synv_total = syn;  // every lane of the slot holds the whole syndrome
+                } else {
+                    if ((t & 63) == 0) synpart[slot * WPS + (t >> 6)] = syn;
+                }
             } else {
                 uint32_t *U = gwords + slot * 2 * NW;
                 const int base = GMap<P, G - 1>::base(t);
@@ -272,13 +296,14 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 }
             }
         }
-        __syncthreads();
+        boundary_sync<WSLOT>();
 
         bool finishing = false, pass = false;
         if constexpr (!GMODE) {
             if (active) {
-                uint32_t s = 0;
-                for (int w = 0; w < WPS; ++w) s ^= synpart[slot * WPS + w];
+                uint32_t s = synv_total;
+                if constexpr (!WSLOT)
+                    for (int w = 0; w < WPS; ++w) s ^= synpart[slot * WPS + w];
                 pass = (s == 0u);
                 finishing = (it + 1 == a.max_iter) || (a.stop == 2 && it + 1 >= a.it_min && pass);
             }
@@ -315,9 +340,9 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             // next LDS writes, at the first L boundary, are ordered behind
             // the cross-wave barriers of this iteration)
             if constexpr (g > 0) {
-                boundary_sync<!GMODE && wave_local_boundary<P, g - 1>(MAPPED_BOUNDARY)>();
+                boundary_sync<WSLOT || (!GMODE && wave_local_boundary<P, g - 1>(MAPPED_BOUNDARY))>();
             } else if constexpr (GMODE) {
-                __syncthreads();
+                boundary_sync<WSLOT>();
             }
         });
 
@@ -340,7 +365,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 gflag[slot] = diff == 0u;
                 for (int i = 0; i < 2 * NW; ++i) U[i] = 0u;
             }
-            __syncthreads();
+            boundary_sync<WSLOT>();
             if (active) {
                 pass = gflag[slot] != 0;
                 finishing = (it + 1 == a.max_iter) || (a.stop == 1 && it + 1 >= a.it_min && pass);
