@@ -63,6 +63,13 @@ def lib() -> ctypes.CDLL:
         L.or_decode.argtypes = [c_i32, c_i32, vp, c_i32, c_u32, vp, c_i64, vp, vp, vp, vp, vp,
                                 vp, c_i32]
         L.or_decode.restype = ctypes.c_int
+        L.or_decode_trace.argtypes = [c_i32, c_i32, vp, c_i32, c_u32, vp, c_i64, vp, vp, vp, vp,
+                                      vp, c_i32, c_i32]
+        L.or_decode_trace.restype = ctypes.c_int
+        L.or_decision_key.argtypes = [c_i32]
+        L.or_decision_key.restype = c_u64
+        L.or_classify.argtypes = [c_i64, c_i32, vp, vp, vp, vp, vp, c_i32, vp, vp]
+        L.or_classify.restype = ctypes.c_int
         L.or_wbp_forward.argtypes = [c_i32, c_i32, vp, vp, c_i64, vp, c_i32, vp, vp]
         L.or_wbp_forward.restype = ctypes.c_int
         L.or_wbp_backward.argtypes = [c_i32, c_i32, vp, vp, c_i64, vp, c_i32, vp, vp, vp, vp]
@@ -252,6 +259,56 @@ def decode(code: Code, llr: np.ndarray, params: DecodeParams, soft: bool = False
     if rc:
         raise ValueError(f"or_decode rc={rc}")
     return DecodeResult(msg, it, ok, su, st)
+
+
+CORRECT, FALSE_CONVERGED, OSCILLATION, UNCONVERGED = 0, 1, 2, 3
+
+
+def decode_trace(code: Code, llr: np.ndarray, params: DecodeParams, H: int,
+                 threads: int = 1):
+    """``decode`` that also records the decision hash after every iteration.
+
+    Returns (DecodeResult, hist uint64 [F, H]); the hash after iteration it
+    (1-based) sits in column (it - 1) mod H; columns a frame did not reach
+    stay 0."""
+    llr = np.ascontiguousarray(llr, np.float32)
+    F = llr.shape[0]
+    assert llr.shape[1] == code.N
+    msg = np.zeros((F, code.K_msg), np.uint8)
+    it = np.zeros(F, np.int32)
+    ok = np.zeros(F, np.uint8)
+    hist = np.zeros((F, H), np.uint64)
+    p = params._c()
+    rc = lib().or_decode_trace(code.N, code.K, _ptr(code.info_idx), code.crc_width, code.crc_poly,
+                               _ptr(llr) if F else None, F, ctypes.byref(p),
+                               _ptr(msg) if F else None, _ptr(it) if F else None,
+                               _ptr(ok) if F else None, _ptr(hist) if F else None, H, threads)
+    if rc:
+        raise ValueError(f"or_decode_trace rc={rc}")
+    return DecodeResult(msg, it, ok), hist
+
+
+def decision_key(j: int) -> int:
+    return int(lib().or_decision_key(j))
+
+
+def classify(msg_hat: np.ndarray, msg: np.ndarray, ok: np.ndarray, iters: np.ndarray,
+             hist: np.ndarray):
+    """Error class (CORRECT .. UNCONVERGED) and decision period of each frame."""
+    msg_hat = np.ascontiguousarray(msg_hat, np.uint8)
+    msg = np.ascontiguousarray(msg, np.uint8)
+    ok = np.ascontiguousarray(ok, np.uint8)
+    iters = np.ascontiguousarray(iters, np.int32)
+    hist = np.ascontiguousarray(hist, np.uint64)
+    F, K_msg = msg_hat.shape
+    H = hist.shape[1]
+    cls = np.zeros(F, np.uint8)
+    per = np.zeros(F, np.int32)
+    rc = lib().or_classify(F, K_msg, _ptr(msg_hat), _ptr(msg), _ptr(ok), _ptr(iters), _ptr(hist),
+                           H, _ptr(cls), _ptr(per))
+    if rc:
+        raise ValueError(f"or_classify rc={rc}")
+    return cls, per
 
 
 @dataclass

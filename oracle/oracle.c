@@ -329,6 +329,23 @@ static int check_g(const code_t *c, const double *Lu, const double *Ru, const do
     return 1;
 }
 
+/* Decision history for the error classes of Sec. II-C.  After every
+ * iteration the hard decisions on level n+1 are summarised by a 64-bit
+ * Zobrist hash: the xor, over the rows j whose decision is 1, of key(j), the
+ * first SplitMix64 output from state j.  Equal decision vectors give equal
+ * hashes; two different ones collide with probability about 2^-64.        */
+static uint64_t decision_key(int32_t j) {
+    uint64_t st = (uint64_t)j;
+    return or_splitmix64_next(&st);
+}
+
+static uint64_t decision_hash(const code_t *c, const double *Lu, const double *Ru, int fp32) {
+    uint64_t h = 0;
+    for (int32_t j = 0; j < c->N; j++)
+        if (hard(Lu[j], Ru[j], fp32)) h ^= decision_key(j);
+    return h;
+}
+
 /* One processing element (Sec. II-B, the four PE equations).  Top row j has
  * bit b = 0, bottom row jp = j | 2^b.  *_in,1 belong to the top row and
  * *_in,2 to the bottom row; L messages arrive from the channel side (lev s-1),
@@ -547,6 +564,8 @@ typedef struct {
     uint8_t *ok;
     double *soft_u;
     double *state;
+    uint64_t *hist; /* [F][H] decision hashes, or NULL */
+    int32_t H;
     int rc;
 } job_t;
 
@@ -582,6 +601,9 @@ static void decode_frames(job_t *jb) {
         int okv = 0;
         for (int32_t it = 1; it <= p->max_iter; it++) {
             one_iteration(&ar, N, &sc, L, R);
+            if (jb->hist)
+                jb->hist[f * jb->H + (it - 1) % jb->H] =
+                    decision_hash(c, L + (size_t)n * N, R + (size_t)n * N, p->fp32);
             if (p->stop != 0 && it >= p->it_min) {
                 int pass = (p->stop == 2)
                                ? check_crc(c, L + (size_t)n * N, R + (size_t)n * N, p->fp32, scratch)
@@ -640,13 +662,16 @@ static void *decode_thread(void *arg) {
 
 /* Decode F frames.  llr: [F][N] float; msg_hat: [F][K - crc_width];
  * iters, ok: [F] or NULL; soft_u: [F][N] L messages at level n+1 after the
- * final L sweep, or NULL; state: [F][2][n+1][N] final L then R, or NULL.
+ * final L sweep, or NULL; state: [F][2][n+1][N] final L then R, or NULL;
+ * hist: [F][H] decision hashes, the one after iteration it (1-based) at
+ * (it - 1) mod H, or NULL (1 <= H <= 64).
  * The frames are split into contiguous chunks over nthreads threads.        */
-int or_decode(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
-              uint32_t crc_poly, const float *llr, int64_t F, const or_params *p,
-              uint8_t *msg_hat, int32_t *iters, uint8_t *ok, double *soft_u,
-              double *state, int32_t nthreads) {
+static int decode_impl(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
+                       uint32_t crc_poly, const float *llr, int64_t F, const or_params *p,
+                       uint8_t *msg_hat, int32_t *iters, uint8_t *ok, double *soft_u,
+                       double *state, uint64_t *hist, int32_t H, int32_t nthreads) {
     int n = ilog2_exact(N);
+    if (hist && (H < 1 || H > 64)) return OR_EINVAL;
     if (n < 0 || K < 1 || K > N || !info_idx || !p || !msg_hat || (F > 0 && !llr)) return OR_EINVAL;
     if (crc_width < 0 || crc_width >= K || p->max_iter < 1) return OR_EINVAL;
     if (p->stop == 2 && crc_width == 0) return OR_EINVAL;
@@ -680,6 +705,8 @@ int or_decode(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
         jb->f0 = F * t / nthreads; jb->f1 = F * (t + 1) / nthreads;
         jb->msg_hat = msg_hat; jb->iters = iters; jb->ok = ok; jb->soft_u = soft_u;
         jb->state = state;
+        jb->hist = hist;
+        jb->H = H;
     }
     if (nthreads == 1) {
         decode_frames(&jobs[0]);
@@ -691,6 +718,71 @@ int or_decode(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
 done:
     free(jobs); free(th); free(c.frozen); free(pool);
     return rc;
+}
+
+int or_decode(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
+              uint32_t crc_poly, const float *llr, int64_t F, const or_params *p,
+              uint8_t *msg_hat, int32_t *iters, uint8_t *ok, double *soft_u,
+              double *state, int32_t nthreads) {
+    return decode_impl(N, K, info_idx, crc_width, crc_poly, llr, F, p, msg_hat, iters, ok, soft_u,
+                       state, NULL, 0, nthreads);
+}
+
+int or_decode_trace(int32_t N, int32_t K, const int32_t *info_idx, int32_t crc_width,
+                    uint32_t crc_poly, const float *llr, int64_t F, const or_params *p,
+                    uint8_t *msg_hat, int32_t *iters, uint8_t *ok, uint64_t *hist, int32_t H,
+                    int32_t nthreads) {
+    if (F > 0 && !hist) return OR_EINVAL;
+    return decode_impl(N, K, info_idx, crc_width, crc_poly, llr, F, p, msg_hat, iters, ok, NULL,
+                       NULL, hist, H, nthreads);
+}
+
+uint64_t or_decision_key(int32_t j) { return decision_key(j); }
+
+/* Error classes of Sec. II-C for decoded frames, given the transmitted
+ * messages.  The paper describes the three kinds of failure in words only:
+ * a decoder that settles on a wrong word (false converged), one whose
+ * decisions cycle between words (oscillation), and one that does neither
+ * (unconverged).  Reading used here, on the last W = min(H, iters) decision
+ * hashes h_1..h_W of a frame (oldest first):
+ *   period p = the smallest p in 1..floor(W/2) with h_i = h_{i+p} for every
+ *   i in 1..W-p, or 0 if there is none;
+ *   class 0 (correct): the decided message equals the transmitted one;
+ *   class 1 (false converged): wrong, and the stop test accepted the final
+ *   decisions (ok) or they are stationary (p = 1);
+ *   class 2 (oscillation): wrong, not accepted, p >= 2;
+ *   class 3 (unconverged): wrong, not accepted, p = 0.
+ * msg_hat, msg: [F][K_msg]; ok: [F]; iters: [F] (>= 1); hist: [F][H] as
+ * written by or_decode_trace; cls: [F]; period: [F] or NULL.                 */
+int or_classify(int64_t F, int32_t K_msg, const uint8_t *msg_hat, const uint8_t *msg,
+                const uint8_t *ok, const int32_t *iters, const uint64_t *hist, int32_t H,
+                uint8_t *cls, int32_t *period) {
+    if (F < 0 || K_msg < 1 || H < 1 || H > 64) return OR_EINVAL;
+    if (F > 0 && (!msg_hat || !msg || !ok || !iters || !hist || !cls)) return OR_EINVAL;
+    for (int64_t f = 0; f < F; f++) {
+        int wrong = 0;
+        for (int32_t i = 0; i < K_msg; i++)
+            if (msg_hat[f * K_msg + i] != msg[f * K_msg + i]) wrong = 1;
+        int32_t it = iters[f];
+        int32_t W = it < H ? it : H;
+        uint64_t seq[64];
+        for (int32_t i = 0; i < W; i++) seq[i] = hist[f * H + (it - W + i) % H];
+        int32_t per = 0;
+        for (int32_t p = 1; 2 * p <= W && per == 0; p++) {
+            int match = 1;
+            for (int32_t i = 0; i + p < W; i++)
+                if (seq[i] != seq[i + p]) match = 0;
+            if (match) per = p;
+        }
+        uint8_t k;
+        if (!wrong) k = 0;
+        else if (ok[f] || per == 1) k = 1;
+        else if (per >= 2) k = 2;
+        else k = 3;
+        cls[f] = k;
+        if (period) period[f] = per;
+    }
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------------ */
