@@ -159,6 +159,38 @@ int pp_mt_bp_decode_ex(const pc_code *code, const float *d_llr, int64_t F,
                        int32_t *d_iters, uint8_t *d_ok, float *d_soft_u,
                        const pc_launch_cfg *cfg, void *stream);
 
+/* Error classes of Sec. II-C.  The paper names three ways BP fails (after
+ * the error classification it cites) and describes them in words only; this
+ * library detects them from the history of the hard decisions.
+ *
+ * pp_mt_bp_decode_trace: pp_mt_bp_decode (any pp mode, or pp NULL for plain
+ * BP) that also records, after every iteration it = 1, 2, ... of frame f,
+ * the 64-bit hash of the decisions on level n+1 at d_hist[f*H + (it-1) % H]:
+ * the xor, over the rows j decided 1, of key(j) = the first SplitMix64
+ * output from state j.  d_hist uint64 [F][H], 8-byte aligned, 1 <= H <= 64;
+ * entries of iterations a frame did not reach are left untouched.  Launch
+ * shape: the library's default (two rows per thread).
+ *
+ * polar_classify_errors: for each frame, on the last W = min(H, iters[f])
+ * recorded hashes h_1..h_W (oldest first), the decision period p is the
+ * smallest p in 1..floor(W/2) with h_i = h_{i+p} for all i <= W-p, else 0
+ * (d_period int32 [F], or NULL).  Class (d_class uint8 [F]): PC_ERR_CORRECT
+ * if d_msg_hat equals d_msg (uint8 [F][K_msg] each); otherwise
+ * PC_ERR_FALSE_CONVERGED if the stop test accepted the final decisions
+ * (d_ok) or p = 1, PC_ERR_OSCILLATION if p >= 2, else PC_ERR_UNCONVERGED.
+ * d_iters, d_ok as written by the decode call; the history must come from a
+ * trace call with the same H.                                              */
+#define PC_ERR_CORRECT 0
+#define PC_ERR_FALSE_CONVERGED 1
+#define PC_ERR_OSCILLATION 2
+#define PC_ERR_UNCONVERGED 3
+int pp_mt_bp_decode_trace(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
+                          const pc_pp_params *pp, uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok,
+                          uint64_t *d_hist, int32_t H, void *stream);
+int polar_classify_errors(const uint8_t *d_msg_hat, const uint8_t *d_msg, const uint8_t *d_ok,
+                          const int32_t *d_iters, const uint64_t *d_hist, int32_t H, int64_t F,
+                          int32_t K_msg, uint8_t *d_class, int32_t *d_period, void *stream);
+
 /* Batched decoding of frames of mixed length and rate in one persistent
  * launch fed from a device work queue.  codes[0..n_codes) (n_codes <= 32)
  * are codes built on this device, each with N in [64, 1024] and a CRC;

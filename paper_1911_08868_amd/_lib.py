@@ -17,7 +17,9 @@ EXPORTS = [
     "polar_encode", "bp_decode", "pp_mt_bp_decode", "pp_mt_bp_decode_ex",
     "polar_batched_workspace_bytes", "pp_mt_bp_decode_batched", "wbp_workspace_bytes",
     "wbp_forward", "wbp_backward", "polar_strerror", "polar_last_error",
+    "pp_mt_bp_decode_trace", "polar_classify_errors",
 ]
+ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED = 0, 1, 2, 3
 
 
 class PolarError(RuntimeError):
@@ -78,6 +80,9 @@ def lib() -> ctypes.CDLL:
                             ctypes.c_int),
         "pp_mt_bp_decode_ex": ([vp, vp, i64, P(BPParamsC), P(PPParamsC), vp, vp, vp, vp,
                                 P(LaunchCfgC), vp], ctypes.c_int),
+        "pp_mt_bp_decode_trace": ([vp, vp, i64, P(BPParamsC), P(PPParamsC), vp, vp, vp, vp, i32,
+                                   vp], ctypes.c_int),
+        "polar_classify_errors": ([vp, vp, vp, vp, vp, i32, i64, i32, vp, vp, vp], ctypes.c_int),
         "polar_batched_workspace_bytes": ([i64], sz),
         "pp_mt_bp_decode_batched": ([vp, i32, vp, vp, vp, i64, P(BPParamsC), P(PPParamsC),
                                      vp, vp, vp, vp, vp, sz, P(LaunchCfgC), vp], ctypes.c_int),

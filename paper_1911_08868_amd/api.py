@@ -174,6 +174,47 @@ def pp_mt_bp_decode(code: Code, llr, bp: BPParams, pp: PPParams, out=None, soft:
     return _decode(code, llr, bp, pp, soft, cfg, out)
 
 
+def pp_mt_bp_decode_trace(code: Code, llr, bp: BPParams, pp: PPParams | None, H: int = 32):
+    """Decode and record the decision hash after every iteration (error
+    classes, Sec. II-C).  Returns (msg_hat, iters, ok, hist [F, H]); hist
+    holds the 64-bit hashes in an int64 tensor (same bits; view the host copy
+    as uint64); the hash after iteration it (1-based) is at column
+    (it - 1) mod H, columns a frame did not reach hold 0."""
+    torch = _torch()
+    F = llr.shape[0]
+    _need(llr, torch.float32, (F, code.N), "llr")
+    dev = llr.device
+    msg = torch.empty((F, code.K_msg), dtype=torch.uint8, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev)
+    ok = torch.empty(F, dtype=torch.uint8, device=dev)
+    hist = torch.zeros((F, H), dtype=torch.int64, device=dev)
+    bpc = bp.c()
+    ppc = (pp or PPParams()).c()
+    check(lib().pp_mt_bp_decode_trace(code.handle, _ptr(llr), F, ctypes.byref(bpc),
+                                      ctypes.byref(ppc), _ptr(msg), _ptr(iters), _ptr(ok),
+                                      _ptr(hist), H, _stream(dev)), "pp_mt_bp_decode_trace")
+    return msg, iters, ok, hist
+
+
+def classify_errors(msg_hat, msg, ok, iters, hist):
+    """Error class (ERR_*) and decision period of each frame from a trace
+    decode's outputs and the transmitted messages (all device tensors)."""
+    torch = _torch()
+    F, K_msg = msg_hat.shape
+    H = hist.shape[1]
+    _need(msg_hat, torch.uint8, (F, K_msg), "msg_hat")
+    _need(msg, torch.uint8, (F, K_msg), "msg")
+    _need(ok, torch.uint8, (F,), "ok")
+    _need(iters, torch.int32, (F,), "iters")
+    _need(hist, torch.int64, (F, H), "hist")
+    cls = torch.empty(F, dtype=torch.uint8, device=msg_hat.device)
+    per = torch.empty(F, dtype=torch.int32, device=msg_hat.device)
+    check(lib().polar_classify_errors(_ptr(msg_hat), _ptr(msg), _ptr(ok), _ptr(iters), _ptr(hist),
+                                      H, F, K_msg, _ptr(cls), _ptr(per), _stream(msg_hat.device)),
+          "polar_classify_errors")
+    return cls, per
+
+
 def batched_workspace_bytes(F: int) -> int:
     return int(lib().polar_batched_workspace_bytes(F))
 

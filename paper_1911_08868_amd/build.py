@@ -2,7 +2,8 @@
 
 Every translation unit is compiled in parallel into ``_build/`` and linked
 in-tree, so the library travels with the source tree.  The decode kernels are
-instantiated once per block length (PBP_NLOG = 1..12) in separate objects.
+instantiated once per block length (PBP_NLOG = 1..12) in separate objects,
+and once more per length for the decision-history variants.
 """
 from __future__ import annotations
 
@@ -34,9 +35,12 @@ def _units():
     units = []
     for n in range(1, 13):
         units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
+    for n in range(1, 13):
+        units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_trace_n{n:02d}.o",
+                      [f"-DPBP_NLOG={n}", "-DPBP_TRACE=1"]))
     for n in range(4, 13):
         units.append((os.path.join(CSRC, "wbp_inst.hip"), f"wbp_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
-    for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip", "alg1.hip"):
+    for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip", "alg1.hip", "diag.hip"):
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         units.append((os.path.join(CSRC, src), os.path.splitext(src)[0] + ".o", lang))
     return units

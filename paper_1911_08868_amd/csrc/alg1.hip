@@ -57,14 +57,9 @@ struct Alg1Args {
     float alpha;
     int32_t P_range, P_level, D, N_min, first_reset;
     uint64_t seed;
+    uint64_t *hist;  // [F][H] decision hashes, or NULL
+    int32_t H;
 };
-
-__device__ __forceinline__ uint64_t splitmix64_next(uint64_t &s) {
-    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 // uniform integer in [0, m): the high 32 bits of the next output, scaled by m
 __device__ __forceinline__ uint32_t draw_below(uint64_t &s, uint32_t m) {
@@ -77,7 +72,7 @@ struct Alg1Lds {
     static constexpr int N = 1 << NLOG, n = NLOG;
     static constexpr size_t msg_floats = (size_t)(2 * n + 1) * N;  // L levels 0..n, R levels 1..n
     static constexpr size_t ord_bytes = ((size_t)N * n + 15) & ~(size_t)15;
-    static constexpr size_t bytes = msg_floats * 4 + ord_bytes + (size_t)N * 4 + 64 * 4;
+    static constexpr size_t bytes = msg_floats * 4 + ord_bytes + (size_t)N * 4 + 128 * 4;
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
@@ -92,7 +87,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
     int8_t *const ord = reinterpret_cast<int8_t *>(smem + Lay::msg_floats);  // [n][N]: bit of stage s of row j at (s-1) N + j
     int32_t *const lab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ord) + Lay::ord_bytes);
     // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
-    // counts, [40 + s] stage s pairs across waves
+    // counts, [40 + s] stage s pairs across waves, [64..95] wave partials of
+    // the decision hash (lo, hi)
     int32_t *const misc = lab + N;
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
@@ -191,6 +187,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         }
         update_cross(row, j);
         load_pairs(row, j);
+        const uint64_t hkey = a.hist ? decision_key(j) : 0ull;
 
         int it_done = a.max_iter;
         bool okv = false;
@@ -212,8 +209,26 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
             });
             // ---- decision and CRC syndrome on level n+1 ----
             uint32_t syn = 0;
-            if (row && Lown[n] + Rown[n] < 0.f) syn = a.syn[j];
+            const bool one = row && Lown[n] + Rown[n] < 0.f;
+            if (one) syn = a.syn[j];
+            if (a.hist) {
+                // decision hash of this iteration (error classes, Sec. II-C);
+                // the partials are read after wg_xor's barriers and rewritten
+                // only after the next iteration's
+                const uint64_t h = one ? hkey : 0ull;
+                const uint32_t lo = lanes_xor<64>((uint32_t)h), hi = lanes_xor<64>((uint32_t)(h >> 32));
+                if (lane == 0) {
+                    misc[64 + 2 * wave] = (int32_t)lo;
+                    misc[65 + 2 * wave] = (int32_t)hi;
+                }
+            }
             const bool pass = wg_xor(syn) == 0u;
+            if (a.hist && tid == 0) {
+                uint64_t h = 0;
+                for (int w = 0; w < nwaves; ++w)
+                    h ^= ((uint64_t)(uint32_t)misc[65 + 2 * w] << 32) | (uint32_t)misc[64 + 2 * w];
+                a.hist[frame * a.H + (it - 1) % a.H] = h;
+            }
             if (a.stop == PC_STOP_CRC && it >= a.it_min && pass) {
                 it_done = it;
                 okv = true;
@@ -367,7 +382,7 @@ __global__ void k_alg1_reset_counter(uint32_t *c) { *c = 0u; }
 
 int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_params &bp,
                 const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
-                hipStream_t s) {
+                uint64_t *d_hist, int32_t H, hipStream_t s) {
     const int n = c->n;
     if (n < 4 || n > 10) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for N = 16 .. 1024");
     if (bp.stop == PC_STOP_G || (bp.stop == PC_STOP_NONE && c->crc_width == 0))
@@ -400,6 +415,8 @@ int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_par
     a.N_min = pp.N_min;
     a.first_reset = pp.first_reset;
     a.seed = pp.seed;
+    a.hist = d_hist;
+    a.H = H;
     const bool scaled = bp.alpha != 1.0f;
     switch (n) {
         case 4: return run_alg1_n<4>(a, scaled, s);

@@ -56,6 +56,7 @@ struct BatchedArgs {
 
 template <int N_>
 struct BatchSrc {
+    static constexpr bool kTrace = false;
     const BatchedArgs &a;
     int64_t F;
     int b, count, start;
@@ -75,6 +76,7 @@ struct BatchSrc {
         if (a.iters) a.iters[f] = iters;
         if (a.ok) a.ok[f] = pass ? 1 : 0;
     }
+    __device__ void trace(int64_t, int, uint64_t) const {}
 };
 
 __global__ void k_batch_clear(int32_t *ctl) {

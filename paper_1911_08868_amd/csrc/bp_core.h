@@ -320,4 +320,21 @@ __device__ __forceinline__ uint32_t lanes_xor(uint32_t v) {
     return v;
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014): add the golden-ratio increment, then
+// two xor-shift-multiply rounds.
+__device__ __forceinline__ uint64_t splitmix64_next(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Zobrist key of row j for the decision history (error classes, Sec. II-C):
+// the first SplitMix64 output from state j.  The hash of a decision vector
+// is the xor of the keys of its ones.
+__device__ __forceinline__ uint64_t decision_key(int j) {
+    uint64_t s = (uint64_t)(uint32_t)j;
+    return splitmix64_next(s);
+}
+
 }  // namespace pbp

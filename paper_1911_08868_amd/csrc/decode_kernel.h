@@ -35,6 +35,8 @@ struct DecodeArgs {
     float alpha;
     int32_t T, Q;
     int8_t orders[8][16];
+    uint64_t *hist;  // [F][H] decision hashes (trace kernels only)
+    int32_t H;
 };
 
 template <class P>
@@ -45,6 +47,7 @@ struct DecodeLds {
         return (size_t)S * 4 * LdsPad<P>::words * sizeof(float)  // L/R boundary ping-pong buffers
                + (size_t)S * sizeof(int)                // frame of each slot
                + (size_t)S * P::WPS * sizeof(uint32_t)  // syndrome partials
+               + (size_t)S * P::WPS * 2 * sizeof(uint32_t)  // decision-hash partials
                + (size_t)S * 2 * NW * sizeof(uint32_t)  // G test words (u_hat, x_hat)
                + (size_t)S * sizeof(int)                // G test verdict
                + 8 * 16;                                // stage orders of the pool
@@ -57,10 +60,10 @@ constexpr int decode_launch_bound() {
     return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
 }
 // waves per SIMD the register allocation must allow: 4 (<= 128 VGPRs) for
-// two rows per thread, 2 for eight
-template <int RHO>
+// two rows per thread, 2 for eight or for the decision-history kernels
+template <int RHO, bool TRACE = false>
 constexpr int decode_min_waves() {
-    return RHO <= 2 ? 4 : 2;
+    return RHO <= 2 && !TRACE ? 4 : 2;
 }
 
 // Iteration parameters shared by every frame source.
@@ -74,6 +77,8 @@ struct DecodeCtl {
 // The lock-step slot loop.  Src supplies frames: pop() (slot leader only)
 // returns the next frame or a value >= Src::F when the queue is empty;
 // per frame it gives the LLR pointer, the code tables and the output sinks.
+// With Src::kTrace the loop also hashes every iteration's decisions
+// (decision_key) and hands the hash to Src::trace (slot leader only).
 // tid is the thread's index in the workgroup (threadIdx.x, or a copy the
 // caller has hidden from the optimiser).
 template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, class Src>
@@ -90,6 +95,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     // barrier in the loop (refill, syndrome and G test stay inside the wave)
     // and leaves when none of its slots has a frame.
     constexpr bool WSLOT = TPS <= 64;
+    constexpr bool TRACE = Src::kTrace;
 
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
@@ -99,7 +105,8 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     float *const buf = smem + (size_t)slot * 4 * NP;  // [L0 | L1 | R0 | R1]
     int *const frame_slot = reinterpret_cast<int *>(smem + (size_t)S * 4 * NP);
     uint32_t *const synpart = reinterpret_cast<uint32_t *>(frame_slot + S);
-    uint32_t *const gwords = synpart + S * WPS;
+    uint32_t *const hpart = synpart + S * WPS;  // [slot][wave][lo, hi]
+    uint32_t *const gwords = hpart + S * WPS * 2;
     int *const gflag = reinterpret_cast<int *>(gwords + S * 2 * NW);
     int8_t *const ords = reinterpret_cast<int8_t *>(gflag + S);
 
@@ -114,6 +121,8 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     uint32_t synv[ROWS];
     float prior[ROWS];  // R on level n+1 of this thread's rows: +inf frozen, 0 information
     int baddr[ROWS];  // byte offsets of the relabelled boundary rows
+    uint64_t hkey[TRACE ? ROWS : 1];  // decision keys of this thread's rows
+    uint64_t htotal = 0;               // the slot's decision hash (one-wave frames)
     uint32_t ubits = 0;
     uint32_t synv_total = 0;  // the slot's syndrome (one-wave frames)
     int it = 0, q = 0, next_ev = 0;
@@ -137,6 +146,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             const int m = tmeta[j];
             synv[i] = tsyn[j];
             prior[i] = m == -2 ? inf : 0.f;
+            if constexpr (TRACE) hkey[i] = decision_key(j);
         });
         if constexpr (MAPPED_BOUNDARY) {
             const int bb = GMap<P, GB>::base(t);
@@ -254,6 +264,8 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             // rows accumulates their columns
             uint32_t syn = 0;
             sfor<0, ROWS>([&](auto i) { syn ^= decide(i) ? synv[i] : 0u; });
+            uint64_t hh = 0;
+            if constexpr (TRACE) sfor<0, ROWS>([&](auto i) { hh ^= decide(i) ? hkey[i] : 0ull; });
             if constexpr (GMODE) {
                 ubits = 0;
                 sfor<0, ROWS>([&](auto i) { ubits |= (decide(i) ? 1u : 0u) << i; });
@@ -267,6 +279,16 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 } else {
                     const int pb = GMap<P, G - 1>::pbase(t);
                     sfor<0, ROWS>([&](auto i) { rt[pb + GMap<P, G - 1>::poff(i)] = rb[i]; });
+                }
+            }
+            if constexpr (TRACE) {
+                const uint32_t lo = lanes_xor<(TPS < 64 ? TPS : 64)>((uint32_t)hh);
+                const uint32_t hi = lanes_xor<(TPS < 64 ? TPS : 64)>((uint32_t)(hh >> 32));
+                if constexpr (WSLOT) {
+                    htotal = ((uint64_t)hi << 32) | lo;
+                } else if ((t & 63) == 0) {
+                    hpart[(slot * WPS + (t >> 6)) * 2] = lo;
+                    hpart[(slot * WPS + (t >> 6)) * 2 + 1] = hi;
                 }
             }
             if constexpr (!GMODE) {
@@ -297,6 +319,18 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             }
         }
         boundary_sync<WSLOT>();
+
+        if constexpr (TRACE) {
+            if (active) {
+                uint64_t h = htotal;
+                if constexpr (!WSLOT) {
+                    h = 0;
+                    for (int w = 0; w < WPS; ++w)
+                        h ^= ((uint64_t)hpart[(slot * WPS + w) * 2 + 1] << 32) | hpart[(slot * WPS + w) * 2];
+                }
+                if (t == 0) src.trace(frame, it, h);
+            }
+        }
 
         bool finishing = false, pass = false;
         if constexpr (!GMODE) {
@@ -410,8 +444,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
 // ---------------------------------------------------------------------------
 // Frame source of a single-code launch: a queue counter over frames 0..F-1.
-template <int N_>
+// With TR it records the decision hash of iteration it (0-based) of frame f
+// at hist[f][it mod H].
+template <int N_, bool TR>
 struct SingleSrc {
+    static constexpr bool kTrace = TR;
     const DecodeArgs &a;
     int64_t F;
     __device__ SingleSrc(const DecodeArgs &args) : a(args), F(args.F) {}
@@ -426,16 +463,19 @@ struct SingleSrc {
         if (a.iters) a.iters[f] = iters;
         if (a.ok) a.ok[f] = pass ? 1 : 0;
     }
+    __device__ void trace(int64_t f, int it, uint64_t h) const {
+        if constexpr (TR) a.hist[f * a.H + it % a.H] = h;
+    }
 };
 
-template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE>
-__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO>()))
+template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, bool TRACE>
+__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO, TRACE>()))
 k_decode(DecodeArgs a) {
     extern __shared__ __align__(16) float smem[];
     constexpr int TPS = Plan<NLOG, KP, RHO>::TPS;
     const int S = blockDim.x / TPS;
     DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0]};
-    SingleSrc<(1 << NLOG)> src(a);
+    SingleSrc<(1 << NLOG), TRACE> src(a);
     decode_loop<NLOG, KP, RHO, SCALED, GMODE>(src, c, smem, S, (int)threadIdx.x);
 }
 

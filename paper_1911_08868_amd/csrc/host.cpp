@@ -292,7 +292,8 @@ static int check_bp(const pc_code *code, const pc_bp_params *bp) {
 
 static int decode_common(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
                          const pc_pp_params *pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok,
-                         float *d_soft, const pc_launch_cfg *cfg, void *stream) {
+                         float *d_soft, const pc_launch_cfg *cfg, void *stream,
+                         uint64_t *d_hist = nullptr, int32_t H = 0) {
     if (!code) return fail(PC_EINVAL, "code is NULL");
     if (F < 0 || F > INT32_MAX) return fail(PC_EINVAL, "F must be in [0, 2^31)");
     int rc = check_bp(code, bp);
@@ -307,7 +308,8 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     if (mode == PC_PP_ALG1) {
         if (cfg && (cfg->rho || cfg->slots || cfg->grid))
             return fail(PC_EINVAL, "Algorithm 1 takes no launch shape (one frame per workgroup)");
-        return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, static_cast<hipStream_t>(stream));
+        return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, d_hist, H,
+                           static_cast<hipStream_t>(stream));
     }
     if (mode != PC_PP_NONE && mode != PC_PP_LASTK && mode != PC_PP_FULL)
         return fail(PC_EINVAL, "unknown multi-trellis mode");
@@ -349,9 +351,12 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     a.alpha = bp->alpha;
     a.T = T;
     a.Q = Q;
+    a.hist = d_hist;
+    a.H = H;
     for (int q = 0; q < Q; ++q)
         for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
     L.kp = kp;
+    L.trace = d_hist != nullptr;
     L.scaled = bp->alpha != 1.0f;
     L.gmode = bp->stop == PC_STOP_G || (bp->stop == PC_STOP_NONE && code->crc_width == 0);
     L.F = F;
@@ -379,6 +384,32 @@ int pp_mt_bp_decode_ex(const pc_code *code, const float *d_llr, int64_t F,
                        int32_t *d_iters, uint8_t *d_ok, float *d_soft_u,
                        const pc_launch_cfg *cfg, void *stream) {
     return decode_common(code, d_llr, F, bp, pp, d_msg_hat, d_iters, d_ok, d_soft_u, cfg, stream);
+}
+
+int pp_mt_bp_decode_trace(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
+                          const pc_pp_params *pp, uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok,
+                          uint64_t *d_hist, int32_t H, void *stream) {
+    if (H < 1 || H > 64) return fail(PC_EINVAL, "history length H must be 1..64");
+    if (F > 0 && !d_hist) return fail(PC_EINVAL, "null history buffer");
+    if (F > 0 && reinterpret_cast<uintptr_t>(d_hist) % 8) return fail(PC_EINVAL, "history pointer not 8-byte aligned");
+    return decode_common(code, d_llr, F, bp, pp, d_msg_hat, d_iters, d_ok, nullptr, nullptr, stream,
+                         d_hist, H);
+}
+
+int polar_classify_errors(const uint8_t *d_msg_hat, const uint8_t *d_msg, const uint8_t *d_ok,
+                          const int32_t *d_iters, const uint64_t *d_hist, int32_t H, int64_t F,
+                          int32_t K_msg, uint8_t *d_class, int32_t *d_period, void *stream) {
+    if (F < 0 || F > INT32_MAX) return fail(PC_EINVAL, "F must be in [0, 2^31)");
+    if (H < 1 || H > 64) return fail(PC_EINVAL, "history length H must be 1..64");
+    if (K_msg < 1) return fail(PC_EINVAL, "K_msg must be >= 1");
+    if (F == 0) return PC_OK;
+    if (!d_msg_hat || !d_msg || !d_ok || !d_iters || !d_hist || !d_class)
+        return fail(PC_EINVAL, "null buffer");
+    if (reinterpret_cast<uintptr_t>(d_hist) % 8 || reinterpret_cast<uintptr_t>(d_iters) % 4 ||
+        reinterpret_cast<uintptr_t>(d_period) % 4)
+        return fail(PC_EINVAL, "misaligned history, iteration or period buffer");
+    return launch_classify(d_msg_hat, d_msg, d_ok, d_iters, d_hist, H, F, K_msg, d_class, d_period,
+                           static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

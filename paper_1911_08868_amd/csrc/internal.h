@@ -74,7 +74,12 @@ int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64
 // Algorithm 1 with random subgraphs (per-row stage orders, messages in LDS)
 int launch_alg1(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params &bp,
                 const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
-                hipStream_t stream);
+                uint64_t *d_hist, int32_t H, hipStream_t stream);
+
+// error classes from the decision history (one wave per frame)
+int launch_classify(const uint8_t *d_msg_hat, const uint8_t *d_msg, const uint8_t *d_ok,
+                    const int32_t *d_iters, const uint64_t *d_hist, int32_t H, int64_t F,
+                    int32_t K_msg, uint8_t *d_class, int32_t *d_period, hipStream_t stream);
 
 size_t batched_ws_bytes(int64_t F);
 

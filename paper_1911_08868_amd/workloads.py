@@ -220,11 +220,62 @@ def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
                         f"max 200 iterations, CRC stop", "points": points}
 
 
+def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
+    """Error classes of Sec. II-C (false converged / oscillation /
+    unconverged) for plain BP, the fixed last-4 schedule and Algorithm 1 on
+    the 1024-bit, rate-1/2 CRC-16 code, from the last H decision hashes of
+    each frame; plus the time of the history-recording decode beside the
+    plain one."""
+    import synth
+    code = pbp.Code(1024, 512, 16, 0x1021, 2.5)
+    bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC)
+    scheds = (("bp", None),
+              ("lastk4", pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)),
+              ("alg1", pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)))
+    names = ("correct", "false_converged", "oscillation", "unconverged")
+    points = []
+    for snr in snrs:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(snr * 100) + 7)
+        m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+        x = pbp.encode(code, m)
+        llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
+                                   code.K_msg, gen)
+        row = {"ebn0_db": snr}
+        for name, pp in scheds:
+            pbp.pp_mt_bp_decode_trace(code, llr, bp, pp, H)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            out = pbp.pp_mt_bp_decode_trace(code, llr, bp, pp, H)
+            ev[1].record()
+            ev[2].record()
+            pbp.pp_mt_bp_decode(code, llr, bp, pp or pbp.PPParams())
+            ev[3].record()
+            cls, per = pbp.classify_errors(out[0], m, out[2], out[1], out[3])
+            torch.cuda.synchronize()
+            counts = torch.bincount(cls.long(), minlength=4).tolist()
+            row[name] = {**{k: int(v) for k, v in zip(names, counts)},
+                         "fer": round(1.0 - counts[0] / F, 6),
+                         "oscillation_periods": {int(p): int(c) for p, c in
+                                                 zip(*torch.unique(per[cls == 2], return_counts=True))},
+                         "ms_trace": round(ev[0].elapsed_time(ev[1]), 2),
+                         "ms_plain": round(ev[2].elapsed_time(ev[3]), 2)}
+        points.append(row)
+        _log(f"error classes at {snr} dB: " + ", ".join(
+            f"{n}: fc {row[n]['false_converged']} osc {row[n]['oscillation']} unc {row[n]['unconverged']}"
+            for n, _ in scheds))
+    return {"workload": f"error classes (Sec. II-C) from the last {H} decision hashes, N=1024 K=496+CRC16, "
+                        f"{F} frames per Eb/N0 point, max 200 iterations, CRC stop; plain BP, fixed last-4 "
+                        f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4)", "points": points}
+
+
 def bench_extras(torch, pbp):
     from .batched import bench_mixed
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
-                     ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1)):
+                     ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1),
+                     ("error_classes", error_classes)):
         try:
             out[name] = fn(torch, pbp)
         except Exception as e:  # report the failure in the JSON line, keep the rest
