@@ -254,7 +254,13 @@ int or_trellis_pool(int32_t n, int32_t k, int32_t Q, uint64_t seed, int8_t *orde
  * Min-sum: sign(x) sign(y) min(|x|,|y|), optionally scaled by alpha; the sign
  * is the xor of the two sign bits (so signed zeros follow IEEE sign bits) and
  * the only rounding is that of the scale.
- * Exact boxplus: 2 atanh(tanh(x/2) tanh(y/2)), FP64 only.                   */
+ * Exact boxplus: 2 atanh(tanh(x/2) tanh(y/2)), FP64 only, evaluated as
+ * sgn(x) sgn(y) min(|x|,|y|) + ln(1 + e^-(|x|+|y|)) - ln(1 + e^-||x|-|y||),
+ * the same function written so that it neither saturates nor loses digits
+ * when both tanh factors round to 1 (for a <= b, both forms equal
+ * ln((1 + e^(a+b)) / (e^a + e^b)) on the magnitudes).  A rounding that takes
+ * the magnitude below 0 gives 0; infinite magnitudes enter as the limits
+ * (inf against y gives y, inf against inf gives inf).                      */
 static double minsum(double x, double y, double alpha, int fp32) {
     double m = fmin(fabs(x), fabs(y));
     if (alpha != 1.0) m = rnd(fp32, alpha * m);
@@ -263,13 +269,13 @@ static double minsum(double x, double y, double alpha, int fp32) {
 }
 
 static double boxplus_exact(double x, double y) {
-    if (isinf(x) && isinf(y)) return (signbit(x) != signbit(y)) ? -INFINITY : INFINITY;
-    if (isinf(x)) return signbit(x) ? -y : y;
-    if (isinf(y)) return signbit(y) ? -x : x;
-    double t = tanh(0.5 * x) * tanh(0.5 * y);
-    if (t >= 1.0) return INFINITY;
-    if (t <= -1.0) return -INFINITY;
-    return 2.0 * atanh(t);
+    double ax = fabs(x), ay = fabs(y);
+    double m = fmin(ax, ay);
+    double d = (ax == ay) ? 0.0 : fabs(ax - ay); /* inf - inf: equal magnitudes */
+    double mag = m + log1p(exp(-(ax + ay))) - log1p(exp(-d));
+    if (!(mag > 0.0)) mag = 0.0;
+    int neg = (signbit(x) != 0) != (signbit(y) != 0);
+    return neg ? -mag : mag;
 }
 
 /* ------------------------------------------------------------------------ */

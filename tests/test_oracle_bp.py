@@ -198,3 +198,48 @@ def test_g_stop_semantics(orc):
         assert bool(r.ok[f]) == np.array_equal(orc.polar_transform(uh), xh)
         if r.iters[f] < 40:
             assert r.ok[f] == 1
+
+
+def _boxplus_decimal(x, y):
+    """2 atanh(tanh(x/2) tanh(y/2)) in 150-digit decimal arithmetic."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 150
+        def th(v):  # tanh(v/2) = (e^v - 1) / (e^v + 1)
+            e = Decimal(v).exp()
+            return (e - 1) / (e + 1)
+        t = th(x) * th(y)
+        if t == 0:
+            return 0.0
+        return float(((1 + t) / (1 - t)).ln())
+
+
+_BOX_VALUES = [0.01, 0.5, 1.3, 7.0, 25.0, 40.0, 90.0]
+
+
+@pytest.mark.parametrize("x", _BOX_VALUES + [-v for v in _BOX_VALUES])
+@pytest.mark.parametrize("y", [0.25, 2.0, 7.0, 39.0, 40.0, -3.5, -88.0])
+def test_exact_boxplus_against_high_precision(orc, x, y):
+    # L(u0) of the N = 2 graph with both bits information is l0 boxplus l1;
+    # both tanh factors round to 1 in FP64 beyond |v| of about 38, where the
+    # function is still finite (40 boxplus 40 = 40 - ln 2 + ln(1 + e^-80))
+    x32, y32 = float(np.float32(x)), float(np.float32(y))
+    L, _ = orc.bp_run(np.array([x32, y32], np.float32), np.zeros(2, np.uint8), 1, fp32=False,
+                      exact=True)
+    want = _boxplus_decimal(x32, y32)
+    assert math.isfinite(L[1, 0])
+    assert L[1, 0] == pytest.approx(want, rel=1e-13, abs=1e-15)
+
+
+def test_exact_boxplus_commutes_and_is_bounded(orc):
+    # |x boxplus y| <= min(|x|, |y|), sign = product of the signs, symmetric
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        v = rng.normal(0, 6, 2).astype(np.float32)
+        L, _ = orc.bp_run(v, np.zeros(2, np.uint8), 1, fp32=False, exact=True)
+        f = L[1, 0]
+        assert abs(f) <= min(abs(float(v[0])), abs(float(v[1]))) + 1e-15
+        assert np.sign(f) == np.sign(v[0]) * np.sign(v[1]) or f == 0
+        L2, _ = orc.bp_run(np.array([v[1], v[0]], np.float32), np.zeros(2, np.uint8), 1,
+                           fp32=False, exact=True)
+        assert L2[1, 0] == f                      # commutative
