@@ -53,6 +53,11 @@ def parse():
                     help="launch shape 'rho,slots' (skips the autotuner)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
+    ap.add_argument("--extra", type=str, default="",
+                    help="only run one side workload of paper_1911_08868_amd.workloads "
+                         "(e.g. exact_boxplus, error_classes) and print its JSON")
+    ap.add_argument("--extra-frames", type=int, default=0,
+                    help="frames per point for --extra (0: the workload's default)")
     return ap.parse_args()
 
 
@@ -163,6 +168,11 @@ def main():
     torch.cuda.set_device(0)
     if args.calib_copy:
         calib_copy(torch)
+        return
+    if args.extra:
+        from paper_1911_08868_amd import workloads
+        kw = {"F": args.extra_frames} if args.extra_frames else {}
+        print(json.dumps(getattr(workloads, args.extra)(torch, pbp, **kw)), flush=True)
         return
     code = pbp.Code(N, K, CRC_W, CRC_POLY, DESIGN_DB)
     F = args.frames

@@ -54,14 +54,24 @@ extern "C" {
  * threads and streams.                                                      */
 typedef struct pc_code pc_code;
 
+#define PC_CHECK_MINSUM 0 /* f(x,y) = alpha sgn(x) sgn(y) min(|x|,|y|) (Sec. II-B, IV)  */
+#define PC_CHECK_EXACT 1  /* f(x,y) = x boxplus y = 2 atanh(tanh(x/2) tanh(y/2))      */
+
 /* Decoder iteration parameters (Algorithm 1 inputs N_it,max and stopID, plus
- * the min-sum scale and the first iteration at which the stop test is
- * applied, Sec. IV).                                                        */
+ * the min-sum scale, the first iteration at which the stop test is applied,
+ * Sec. IV, and the check function of the processing element, Sec. II-B).
+ * PC_CHECK_EXACT needs alpha = 1 and is built for the decode entry points
+ * with the default launch shape or rho = 2 (not for Algorithm 1, the batched
+ * decoder or the decision history).  It is evaluated in FP32 as
+ * sgn sgn [min(|x|,|y|) + ln(1 + e^-(|x|+|y|)) - ln(1 + e^-||x|-|y||)] on the
+ * hardware exp2/log2 (about 1e-7 absolute per check node), so it agrees with
+ * an FP64 evaluation to rounding, not bit for bit.                          */
 typedef struct {
     int32_t max_iter; /* N_it,max >= 1                                       */
     float alpha;      /* min-sum scale; 1 = the unscaled min-sum of Sec. IV  */
     int32_t stop;     /* PC_STOP_*                                           */
     int32_t it_min;   /* stop test applied from this iteration on (>= 1)     */
+    int32_t check;    /* PC_CHECK_*                                          */
 } pc_bp_params;
 
 /* Multi-trellis schedule (Sec. II-D, Sec. III).  For PC_PP_LASTK the pool

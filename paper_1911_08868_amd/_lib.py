@@ -19,6 +19,7 @@ EXPORTS = [
     "wbp_forward", "wbp_backward", "polar_strerror", "polar_last_error",
     "pp_mt_bp_decode_trace", "polar_classify_errors",
 ]
+CHECK_MINSUM, CHECK_EXACT = 0, 1
 ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED = 0, 1, 2, 3
 
 
@@ -36,7 +37,7 @@ class PolarError(RuntimeError):
 
 class BPParamsC(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
-                ("stop", ctypes.c_int32), ("it_min", ctypes.c_int32)]
+                ("stop", ctypes.c_int32), ("it_min", ctypes.c_int32), ("check", ctypes.c_int32)]
 
 
 class PPParamsC(ctypes.Structure):

@@ -12,7 +12,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from ._lib import (BPParamsC, LaunchCfgC, PPParamsC, PolarError, PP_ALG1, PP_FULL,  # noqa: F401
-                   PP_LASTK, PP_NONE, STOP_CRC, STOP_G, STOP_NONE, check, lib)
+                   PP_LASTK, PP_NONE, STOP_CRC, STOP_G, STOP_NONE, CHECK_MINSUM, CHECK_EXACT,
+                   check, lib)
 
 
 def _torch():
@@ -47,9 +48,10 @@ class BPParams:
     alpha: float = 1.0
     stop: int = STOP_CRC
     it_min: int = 1
+    check: int = CHECK_MINSUM
 
     def c(self) -> BPParamsC:
-        return BPParamsC(self.max_iter, self.alpha, self.stop, self.it_min)
+        return BPParamsC(self.max_iter, self.alpha, self.stop, self.it_min, self.check)
 
 
 @dataclass

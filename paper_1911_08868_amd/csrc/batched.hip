@@ -205,6 +205,7 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
     if (bp->stop != PC_STOP_CRC && bp->stop != PC_STOP_NONE)
         return fail(PC_ENOTSUP, "batched decoding uses the CRC test (or none)");
     if (!(bp->alpha > 0.f) || !std::isfinite(bp->alpha)) return fail(PC_EINVAL, "alpha must be finite and > 0");
+    if (bp->check != PC_CHECK_MINSUM) return fail(PC_ENOTSUP, "the batched decoder is built for min-sum");
     BatchedArgs a;
     std::memset(&a, 0, sizeof(a));
     for (int i = 0; i < n_codes; ++i) {

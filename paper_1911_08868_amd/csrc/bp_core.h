@@ -173,12 +173,44 @@ __device__ __forceinline__ float cnode(float x, float y, float alpha) {
 // check function, whose zero stays zero, and additions, where a nonzero
 // addend wins) and no decision (-0 and +0 both decide 0), so decoding is
 // unchanged.  The bound x should be the operand less likely to be zero.
-template <bool SCALED>
+//
+// CN selects the check function: 0 min-sum, 1 scaled min-sum, 2 the exact
+// boxplus below.
+__device__ __forceinline__ float cnode_exact(float x, float y);
+
+template <int CN>
 __device__ __forceinline__ float cnode_clamp(float x, float y, float alpha) {
-    const float ax = __builtin_fabsf(x);
-    float t = __builtin_amdgcn_fmed3f(y, ax, -ax);
-    if constexpr (SCALED) t = alpha * t;
-    return __uint_as_float(__float_as_uint(t) ^ (__float_as_uint(x) & 0x80000000u));
+    if constexpr (CN == 2) {
+        return cnode_exact(x, y);
+    } else {
+        const float ax = __builtin_fabsf(x);
+        float t = __builtin_amdgcn_fmed3f(y, ax, -ax);
+        if constexpr (CN == 1) t = alpha * t;
+        return __uint_as_float(__float_as_uint(t) ^ (__float_as_uint(x) & 0x80000000u));
+    }
+}
+
+// ln(1 + e^-d) for d >= 0 (or +inf), in base 2: log2(1 + 2^(-d log2 e)) on
+// v_exp_f32 and v_log_f32; 1 + 2^(...) rounds to 1 once e^-d < 2^-24, where
+// the true value is below 6e-8.
+__device__ __forceinline__ float log2_1p_exp_neg(float d) {
+    return __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(d * -1.44269504088896341f));
+}
+
+// Exact boxplus 2 atanh(tanh(x/2) tanh(y/2)) (Sec. II-B) as
+// sgn(x) sgn(y) [min(|x|,|y|) + ln(1 + e^-(|x|+|y|)) - ln(1 + e^-||x|-|y||)],
+// the same function without the saturation of the tanh form.  Equal
+// magnitudes (also +inf against +inf) take the difference 0; a rounding that
+// takes the magnitude below 0 gives 0; +inf against a finite y gives y.  The
+// magnitude's minimum and the clamp use the IEEE-754-2019 minimum/maximum
+// (no NaN can reach them); the last step is one fused multiply-add.
+__device__ __forceinline__ float cnode_exact(float x, float y) {
+    const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+    const float m = __builtin_elementwise_minimum(ax, ay);
+    const float d = ax == ay ? 0.f : __builtin_fabsf(ax - ay);
+    const float l = log2_1p_exp_neg(ax + ay) - log2_1p_exp_neg(d);
+    const float mag = __builtin_elementwise_maximum(__builtin_fmaf(l, 0.693147180559945309f, m), 0.f);
+    return __uint_as_float(__float_as_uint(mag) ^ ((__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u));
 }
 
 // ---------------------------------------------------------------------------
@@ -196,7 +228,7 @@ struct Regs {
 // R on its interior levels and top level; output L on its interior levels
 // and on its top level (returned in `out`).  `rtop` is the R of the top
 // level (the prior for the last group).
-template <class P, int g, bool SCALED>
+template <class P, int g, int CN>
 __device__ __forceinline__ void group_L(Regs<P> &S, const float (&rtop)[P::ROWS],
                                         float (&out)[P::ROWS], float alpha) {
     constexpr int r = P::size(g);
@@ -217,8 +249,8 @@ __device__ __forceinline__ void group_L(Regs<P> &S, const float (&rtop)[P::ROWS]
                     r2 = rtop[ip];
                 }
                 const float l1 = cur[i], l2 = cur[ip];
-                nxt[i] = cnode_clamp<SCALED>(l1, l2 + r2, alpha);
-                nxt[ip] = cnode_clamp<SCALED>(l1, r1, alpha) + l2;
+                nxt[i] = cnode_clamp<CN>(l1, l2 + r2, alpha);
+                nxt[ip] = cnode_clamp<CN>(l1, r1, alpha) + l2;
             }
         });
         if constexpr (sl + 1 < r) {
@@ -232,7 +264,7 @@ __device__ __forceinline__ void group_L(Regs<P> &S, const float (&rtop)[P::ROWS]
 // R sweep over the stages of group g, top to bottom: input R on its top level
 // (`rtop`), L on its interior and bottom levels; output R on its interior
 // levels and on its bottom level (returned in `out`).
-template <class P, int g, bool SCALED>
+template <class P, int g, int CN>
 __device__ __forceinline__ void group_R(Regs<P> &S, const float (&rtop)[P::ROWS],
                                         float (&out)[P::ROWS], float alpha) {
     constexpr int r = P::size(g);
@@ -254,8 +286,8 @@ __device__ __forceinline__ void group_R(Regs<P> &S, const float (&rtop)[P::ROWS]
                     l2 = S.Lbot[g][ip];
                 }
                 const float r1 = cur[i], r2 = cur[ip];
-                nxt[i] = cnode_clamp<SCALED>(l2 + r2, r1, alpha);
-                nxt[ip] = cnode_clamp<SCALED>(l1, r1, alpha) + r2;
+                nxt[i] = cnode_clamp<CN>(l2 + r2, r1, alpha);
+                nxt[ip] = cnode_clamp<CN>(l1, r1, alpha) + r2;
             }
         });
         if constexpr (sl > 0) {

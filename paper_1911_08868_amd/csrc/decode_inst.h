@@ -12,13 +12,15 @@ struct DecodeLaunch {
     DecodeArgs args;
     int kp = 0;
     bool scaled = false, gmode = false;
-    bool trace = false;  // decision-history kernels (rho 2 only)
+    // kernel family: 0 min-sum, 1 min-sum with decision history, 2 exact
+    // boxplus (1 and 2 are built with two rows per thread only)
+    int variant = 0;
     int rho = 2, slots = 0, grid = 0;
     int64_t F = 0;
     hipStream_t stream = nullptr;
 };
 
-template <int NLOG, int KP, int RHO, bool SC, bool GM, bool TR>
+template <int NLOG, int KP, int RHO, int CN, bool GM, bool TR>
 int run_decode(const DecodeLaunch &L) {
     using P = Plan<NLOG, KP, RHO>;
     const int TPS = P::TPS;
@@ -28,7 +30,7 @@ int run_decode(const DecodeLaunch &L) {
     if (S * TPS > LB) return fail(PC_EINVAL, "slots * threads per frame exceeds the launch bound");
     const size_t lds = DecodeLds<P>::bytes(S);
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for this launch shape");
-    auto kern = k_decode<NLOG, KP, RHO, SC, GM, TR>;
+    auto kern = k_decode<NLOG, KP, RHO, CN, GM, TR>;
     int grid = L.grid;
     if (grid <= 0) {
         int per_cu = 0;
@@ -46,49 +48,55 @@ int run_decode(const DecodeLaunch &L) {
     return PC_OK;
 }
 
-template <int NLOG, int KP, int RHO, bool TR>
-int run_decode_flags(const DecodeLaunch &L) {
-    if constexpr (KP == 0) {
-        if (L.gmode)
-            return L.scaled ? run_decode<NLOG, KP, RHO, true, true, TR>(L)
-                            : run_decode<NLOG, KP, RHO, false, true, TR>(L);
-        return L.scaled ? run_decode<NLOG, KP, RHO, true, false, TR>(L)
-                        : run_decode<NLOG, KP, RHO, false, false, TR>(L);
+template <int NLOG, int KP, int RHO, int V, bool GM>
+int run_decode_check(const DecodeLaunch &L) {
+    if constexpr (V == 2) {
+        return run_decode<NLOG, KP, RHO, 2, GM, false>(L);
     } else {
-        if (L.gmode) return fail(PC_ENOTSUP, "the G test is only built for the original graph");
-        return L.scaled ? run_decode<NLOG, KP, RHO, true, false, TR>(L)
-                        : run_decode<NLOG, KP, RHO, false, false, TR>(L);
+        return L.scaled ? run_decode<NLOG, KP, RHO, 1, GM, V == 1>(L)
+                        : run_decode<NLOG, KP, RHO, 0, GM, V == 1>(L);
     }
 }
 
-template <int NLOG, int RHO, bool TR>
+template <int NLOG, int KP, int RHO, int V>
+int run_decode_flags(const DecodeLaunch &L) {
+    if constexpr (KP == 0) {
+        return L.gmode ? run_decode_check<NLOG, KP, RHO, V, true>(L) : run_decode_check<NLOG, KP, RHO, V, false>(L);
+    } else {
+        if (L.gmode) return fail(PC_ENOTSUP, "the G test is only built for the original graph");
+        return run_decode_check<NLOG, KP, RHO, V, false>(L);
+    }
+}
+
+template <int NLOG, int RHO, int V>
 int run_decode_kp(const DecodeLaunch &L) {
-    if (L.kp == 0) return run_decode_flags<NLOG, 0, RHO, TR>(L);
+    if (L.kp == 0) return run_decode_flags<NLOG, 0, RHO, V>(L);
     if (L.kp == NLOG) {
-        if constexpr (NLOG >= 2) return run_decode_flags<NLOG, NLOG, RHO, TR>(L);
+        if constexpr (NLOG >= 2) return run_decode_flags<NLOG, NLOG, RHO, V>(L);
     }
     switch (L.kp) {
-        case 2: if constexpr (NLOG > 2) return run_decode_flags<NLOG, 2, RHO, TR>(L); break;
-        case 3: if constexpr (NLOG > 3) return run_decode_flags<NLOG, 3, RHO, TR>(L); break;
-        case 4: if constexpr (NLOG > 4) return run_decode_flags<NLOG, 4, RHO, TR>(L); break;
-        case 5: if constexpr (NLOG > 5) return run_decode_flags<NLOG, 5, RHO, TR>(L); break;
+        case 2: if constexpr (NLOG > 2) return run_decode_flags<NLOG, 2, RHO, V>(L); break;
+        case 3: if constexpr (NLOG > 3) return run_decode_flags<NLOG, 3, RHO, V>(L); break;
+        case 4: if constexpr (NLOG > 4) return run_decode_flags<NLOG, 4, RHO, V>(L); break;
+        case 5: if constexpr (NLOG > 5) return run_decode_flags<NLOG, 5, RHO, V>(L); break;
         default: break;
     }
     return fail(PC_ENOTSUP, "permuted range k must be 2..5 or n in this build");
 }
 
-// TR: the decision-history kernels, built with two rows per thread only
-template <int NLOG, bool TR>
+// V: kernel family (DecodeLaunch::variant)
+template <int NLOG, int V>
 int run_decode_n(const DecodeLaunch &L) {
     if constexpr (NLOG == 1) {
-        return run_decode_kp<1, 1, TR>(L);
+        return run_decode_kp<1, 1, V>(L);
     } else {
         if (L.rho == 3) {
-            if constexpr (NLOG >= 3 && !TR) return run_decode_kp<NLOG, 3, TR>(L);
-            return fail(TR ? PC_ENOTSUP : PC_EINVAL, TR ? "decision history is built for rho 2" : "rho exceeds log2 N");
+            if constexpr (NLOG >= 3 && V == 0) return run_decode_kp<NLOG, 3, V>(L);
+            return fail(V ? PC_ENOTSUP : PC_EINVAL,
+                        V ? "decision history and exact boxplus are built for rho 2" : "rho exceeds log2 N");
         }
         if (L.rho != 2) return fail(PC_EINVAL, "rho must be 2 or 3");
-        return run_decode_kp<NLOG, 2, TR>(L);
+        return run_decode_kp<NLOG, 2, V>(L);
     }
 }
 

@@ -1,14 +1,17 @@
-// One block length's decode kernels; built once per PBP_NLOG = 1..12, and
-// once more with PBP_TRACE=1 for the decision-history kernels.
+// One block length's decode kernels; built once per PBP_NLOG = 1..12 for each
+// kernel family PBP_VARIANT (0 min-sum, 1 with decision history, 2 exact
+// boxplus).
 #include "decode_inst.h"
 
 #define PBP_CAT2(a, b) a##b
 #define PBP_CAT(a, b) PBP_CAT2(a, b)
 
 namespace pbp {
-#if PBP_TRACE
-int PBP_CAT(run_decode_trace_n, PBP_NLOG)(const DecodeLaunch &L) { return run_decode_n<PBP_NLOG, true>(L); }
+#if PBP_VARIANT == 1
+int PBP_CAT(run_decode_trace_n, PBP_NLOG)(const DecodeLaunch &L) { return run_decode_n<PBP_NLOG, 1>(L); }
+#elif PBP_VARIANT == 2
+int PBP_CAT(run_decode_exact_n, PBP_NLOG)(const DecodeLaunch &L) { return run_decode_n<PBP_NLOG, 2>(L); }
 #else
-int PBP_CAT(run_decode_n, PBP_NLOG)(const DecodeLaunch &L) { return run_decode_n<PBP_NLOG, false>(L); }
+int PBP_CAT(run_decode_n, PBP_NLOG)(const DecodeLaunch &L) { return run_decode_n<PBP_NLOG, 0>(L); }
 #endif
 }  // namespace pbp

@@ -81,7 +81,7 @@ struct DecodeCtl {
 // (decision_key) and hands the hash to Src::trace (slot leader only).
 // tid is the thread's index in the workgroup (threadIdx.x, or a copy the
 // caller has hidden from the optimiser).
-template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, class Src>
+template <int NLOG, int KP, int RHO, int CN, bool GMODE, class Src>
 __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float *smem, int S, const int tid) {
     using P = Plan<NLOG, KP, RHO>;
     constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG;
@@ -238,7 +238,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                     }
                 }
                 float out[ROWS];
-                group_L<P, g, SCALED>(st, st.Rtop[g], out, alpha);
+                group_L<P, g, CN>(st, st.Rtop[g], out, alpha);
                 float *lt = buf + ((g + 1) & 1) * NP;
                 const int pb = GMap<P, g>::pbase(t);
                 sfor<0, ROWS>([&](auto i) { lt[pb + GMap<P, g>::poff(i)] = out[i]; });
@@ -257,7 +257,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                     sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[pb + GMap<P, G - 1>::poff(i)]; });
                 }
             }
-            group_L<P, G - 1, SCALED>(st, prior, st.Ltop, alpha);
+            group_L<P, G - 1, CN>(st, prior, st.Ltop, alpha);
             // hard decision (Sec. II-B): u = 1 iff L + R < 0 on level n+1,
             // R = +inf (frozen) or 0, i.e. iff L < -R (one compare: never for a
             // frozen row, and -0 decides 0); the CRC syndrome of the decided
@@ -271,7 +271,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 sfor<0, ROWS>([&](auto i) { ubits |= (decide(i) ? 1u : 0u) << i; });
             }
             float rb[ROWS];
-            group_R<P, G - 1, SCALED>(st, prior, rb, alpha);
+            group_R<P, G - 1, CN>(st, prior, rb, alpha);
             if constexpr (G > 1) {
                 float *rt = buf + 2 * NP + ((G - 1) & 1) * NP;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
@@ -351,7 +351,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 const int base = GMap<P, g>::base(t), pb = GMap<P, g>::pbase(t);
                 sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rsrc[pb + GMap<P, g>::poff(i)]; });
                 float rb[ROWS];
-                group_R<P, g, SCALED>(st, st.Rtop[g], rb, alpha);
+                group_R<P, g, CN>(st, st.Rtop[g], rb, alpha);
                 if constexpr (g > 0) {
                     float *rt = buf + 2 * NP + (g & 1) * NP;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
@@ -468,7 +468,7 @@ struct SingleSrc {
     }
 };
 
-template <int NLOG, int KP, int RHO, bool SCALED, bool GMODE, bool TRACE>
+template <int NLOG, int KP, int RHO, int CN, bool GMODE, bool TRACE>
 __global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO, TRACE>()))
 k_decode(DecodeArgs a) {
     extern __shared__ __align__(16) float smem[];
@@ -476,7 +476,7 @@ k_decode(DecodeArgs a) {
     const int S = blockDim.x / TPS;
     DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0]};
     SingleSrc<(1 << NLOG), TRACE> src(a);
-    decode_loop<NLOG, KP, RHO, SCALED, GMODE>(src, c, smem, S, (int)threadIdx.x);
+    decode_loop<NLOG, KP, RHO, CN, GMODE>(src, c, smem, S, (int)threadIdx.x);
 }
 
 }  // namespace pbp

@@ -287,6 +287,8 @@ static int check_bp(const pc_code *code, const pc_bp_params *bp) {
     if (bp->stop < PC_STOP_NONE || bp->stop > PC_STOP_CRC) return fail(PC_EINVAL, "unknown stop test");
     if (bp->stop == PC_STOP_CRC && code->crc_width == 0) return fail(PC_EINVAL, "CRC stop on a code without CRC");
     if (!(bp->alpha > 0.f) || !std::isfinite(bp->alpha)) return fail(PC_EINVAL, "alpha must be finite and > 0");
+    if (bp->check != PC_CHECK_MINSUM && bp->check != PC_CHECK_EXACT) return fail(PC_EINVAL, "unknown check function");
+    if (bp->check == PC_CHECK_EXACT && bp->alpha != 1.0f) return fail(PC_EINVAL, "the exact boxplus takes no scale (alpha = 1)");
     return PC_OK;
 }
 
@@ -305,7 +307,10 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     int kp = 0, T = 1, Q = 1;
     int8_t orders[kMaxPool * kMaxLog] = {0};
     const int n = code->n;
+    const bool exact = bp->check == PC_CHECK_EXACT;
+    if (exact && d_hist) return fail(PC_ENOTSUP, "the decision history is built for min-sum");
     if (mode == PC_PP_ALG1) {
+        if (exact) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for min-sum");
         if (cfg && (cfg->rho || cfg->slots || cfg->grid))
             return fail(PC_EINVAL, "Algorithm 1 takes no launch shape (one frame per workgroup)");
         return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, d_hist, H,
@@ -356,7 +361,7 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     for (int q = 0; q < Q; ++q)
         for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
     L.kp = kp;
-    L.trace = d_hist != nullptr;
+    L.variant = d_hist ? 1 : exact ? 2 : 0;
     L.scaled = bp->alpha != 1.0f;
     L.gmode = bp->stop == PC_STOP_G || (bp->stop == PC_STOP_NONE && code->crc_width == 0);
     L.F = F;

@@ -270,12 +270,60 @@ def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
                         f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4)", "points": points}
 
 
+VALU_PEAK = 256 * 64 * 2.4e9          # non-packed 32-bit VALU lane-slots per second
+EXACT_SLOTS_PER_PE = 2 * (11 + 4) + 2
+
+
+def exact_boxplus(torch, pbp, F=262144, snrs=(1.5, 2.0, 2.5, 3.0, 3.5)):
+    """The exact boxplus check function (Sec. II-B) beside min-sum on the
+    1024-bit, rate-1/2 CRC-16 code with the fixed last-4 schedule (T=10, Q=8),
+    at most 200 iterations, CRC stop, on the same frames."""
+    import synth
+    code = pbp.Code(1024, 512, 16, 0x1021, 2.5)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
+    pes = (2 * 10 - 1) * 512      # PEs per frame-iteration: L sweep 10 stages, R sweep 9
+    points = []
+    for snr in snrs:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(snr * 100) + 11)
+        m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+        x = pbp.encode(code, m)
+        llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
+                                   code.K_msg, gen)
+        row = {"ebn0_db": snr}
+        for name, chk in (("exact", pbp.CHECK_EXACT), ("minsum", pbp.CHECK_MINSUM)):
+            bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, check=chk)
+            out = pbp.pp_mt_bp_decode(code, llr, bp, pp)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            out = pbp.pp_mt_bp_decode(code, llr, bp, pp, out=out[:3])
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            its = out[1].double().sum().item()
+            row[name] = {"gbit_s": round(F * code.K_msg / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
+                         "avg_iters": round(its / F, 3),
+                         "fer": (out[0] != m).any(1).double().mean().item(),
+                         "pe_per_s": round(its * pes / (ms / 1e3), 1)}
+            if name == "exact":
+                # VALU instructions per PE of the exact form: per check node 11
+                # plain ones and 4 transcendental ones (each at least one issue
+                # slot), two check nodes and two additions per PE
+                row[name]["alu_frac"] = round(row[name]["pe_per_s"] * EXACT_SLOTS_PER_PE / VALU_PEAK, 4)
+        points.append(row)
+        _log(f"exact boxplus at {snr} dB: {row['exact']['gbit_s']} Gbit/s fer {row['exact']['fer']:.4g} "
+             f"vs min-sum {row['minsum']['gbit_s']} Gbit/s fer {row['minsum']['fer']:.4g}")
+    return {"workload": f"exact boxplus vs min-sum, N=1024 K=496+CRC16, fixed last-4 (T=10, Q=8), "
+                        f"{F} frames per Eb/N0 point, max 200 iterations, CRC stop", "points": points}
+
+
 def bench_extras(torch, pbp):
     from .batched import bench_mixed
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
                      ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1),
-                     ("error_classes", error_classes)):
+                     ("error_classes", error_classes), ("exact_boxplus", exact_boxplus)):
         try:
             out[name] = fn(torch, pbp)
         except Exception as e:  # report the failure in the JSON line, keep the rest
