@@ -120,7 +120,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     Regs<P> st;
     uint32_t synv[ROWS];
     float prior[ROWS];  // R on level n+1 of this thread's rows: +inf frozen, 0 information
-    int baddr[ROWS];  // byte offsets of the relabelled boundary rows
+    // LDS addresses of the relabelled boundary rows in buffer 0 of this slot:
+    // a 32-bit LDS pointer per row, so every access is one ds instruction
+    // with the buffer's constant offset
+    typedef __attribute__((address_space(3))) float lds_f32;
+    lds_f32 *bptr[ROWS];
     uint64_t hkey[TRACE ? ROWS : 1];  // decision keys of this thread's rows
     uint64_t htotal = 0;               // the slot's decision hash (one-wave frames)
     uint32_t ubits = 0;
@@ -151,7 +155,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         if constexpr (MAPPED_BOUNDARY) {
             const int bb = GMap<P, GB>::base(t);
             sfor<0, ROWS>([&](auto i) {
-                baddr[i] = 4 * LdsPad<P>::at(relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS));
+                bptr[i] = (lds_f32 *)buf + LdsPad<P>::at(relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS));
             });
         }
     };
@@ -231,7 +235,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 if constexpr (g > 0) {
                     const float *lb = buf + (g & 1) * NP;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
-                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = byte_at(lb, baddr[i]); });
+                        sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = bptr[i][(g & 1) * NP]; });
                     } else {
                         const int pb = GMap<P, g>::pbase(t);
                         sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[pb + GMap<P, g>::poff(i)]; });
@@ -251,7 +255,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             if constexpr (G > 1) {
                 const float *lb = buf + ((G - 1) & 1) * NP;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
-                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = byte_at(lb, baddr[i]); });
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = bptr[i][((G - 1) & 1) * NP]; });
                 } else {
                     const int pb = GMap<P, G - 1>::pbase(t);
                     sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[pb + GMap<P, G - 1>::poff(i)]; });
@@ -275,7 +279,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
             if constexpr (G > 1) {
                 float *rt = buf + 2 * NP + ((G - 1) & 1) * NP;
                 if constexpr (MAPPED_BOUNDARY && G - 1 == GB) {
-                    sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
+                    sfor<0, ROWS>([&](auto i) { bptr[i][2 * NP + ((G - 1) & 1) * NP] = rb[i]; });
                 } else {
                     const int pb = GMap<P, G - 1>::pbase(t);
                     sfor<0, ROWS>([&](auto i) { rt[pb + GMap<P, G - 1>::poff(i)] = rb[i]; });
@@ -355,7 +359,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 if constexpr (g > 0) {
                     float *rt = buf + 2 * NP + (g & 1) * NP;
                     if constexpr (MAPPED_BOUNDARY && g == GB) {
-                        sfor<0, ROWS>([&](auto i) { byte_at(rt, baddr[i]) = rb[i]; });
+                        sfor<0, ROWS>([&](auto i) { bptr[i][2 * NP + (g & 1) * NP] = rb[i]; });
                     } else {
                         sfor<0, ROWS>([&](auto i) { rt[pb + GMap<P, g>::poff(i)] = rb[i]; });
                     }
