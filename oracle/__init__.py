@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
         L.or_decode_trace.argtypes = [c_i32, c_i32, vp, c_i32, c_u32, vp, c_i64, vp, vp, vp, vp,
                                       vp, c_i32, c_i32]
         L.or_decode_trace.restype = ctypes.c_int
+        L.or_noise_gauss.argtypes = [c_u64, c_i64, c_i32, c_i32]
+        L.or_noise_gauss.restype = ctypes.c_float
         L.or_decision_key.argtypes = [c_i32]
         L.or_decision_key.restype = c_u64
         L.or_classify.argtypes = [c_i64, c_i32, vp, vp, vp, vp, vp, c_i32, vp, vp]
@@ -100,7 +102,8 @@ class _Params(ctypes.Structure):
                 ("Q", ctypes.c_int32), ("P_range", ctypes.c_int32), ("P_level", ctypes.c_int32),
                 ("D", ctypes.c_int32), ("N_min", ctypes.c_int32),
                 ("first_reset", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("fp32", ctypes.c_int32), ("exact_boxplus", ctypes.c_int32)]
+                ("fp32", ctypes.c_int32), ("exact_boxplus", ctypes.c_int32),
+                ("noise_sigma", ctypes.c_float)]
 
 
 class _WbpParams(ctypes.Structure):
@@ -219,11 +222,13 @@ class DecodeParams:
     seed: int = 0
     fp32: bool = True
     exact_boxplus: bool = False
+    noise_sigma: float = 0.0
 
     def _c(self) -> _Params:
         return _Params(self.max_iter, self.alpha, self.stop, self.it_min, self.pp_mode, self.k,
                        self.T, self.Q, self.P_range, self.P_level, self.D, self.N_min,
-                       self.first_reset, self.seed, int(self.fp32), int(self.exact_boxplus))
+                       self.first_reset, self.seed, int(self.fp32), int(self.exact_boxplus),
+                       self.noise_sigma)
 
 
 @dataclass
@@ -286,6 +291,10 @@ def decode_trace(code: Code, llr: np.ndarray, params: DecodeParams, H: int,
     if rc:
         raise ValueError(f"or_decode_trace rc={rc}")
     return DecodeResult(msg, it, ok), hist
+
+
+def noise_gauss(seed: int, frame: int, e: int, j: int) -> float:
+    return float(lib().or_noise_gauss(seed, frame, e, j))
 
 
 def decision_key(j: int) -> int:

@@ -295,6 +295,7 @@ typedef struct {
     uint64_t seed;
     int32_t fp32;
     int32_t exact_boxplus;
+    float noise_sigma; /* > 0: noise injected at the trellis events (modes 0, 1) */
 } or_params;
 
 typedef struct {
@@ -333,6 +334,30 @@ static int check_g(const code_t *c, const double *Lu, const double *Ru, const do
     for (int32_t j = 0; j < N; j++)
         if (x[j] != hard(L0[j], R0[j], fp32)) return 0;
     return 1;
+}
+
+/* Noise injection at the trellis events.  The paper leaves "noise injection
+ * along with partial permutations" to future work (Sec. V) and compares with
+ * noise-aided BP at sigma^2 = 0.36 (Table I); the reading used here: at every
+ * event of the fixed schedules (after iterations T, 2T, ...; also when the
+ * pool has one entry and the graph stays) the channel level is set to
+ * y_j + sigma g(frame, e, j), e = it / T, with fresh noise per event and the
+ * received LLR y_j.  g is an Irwin-Hall approximation of N(0,1): the sum of
+ * the twelve 16-bit fields of three SplitMix64 outputs, each field k read as
+ * the uniform (k + 1/2) / 2^16, minus 6.  The generator starts from the state
+ * seed ^ frame * 0x9E3779B97F4A7C15 ^ e * 0xC2B2AE3D27D4EB4F
+ * ^ j * 0x165667B19E3779F9.  Every g is a multiple of 2^-16 in (-6, 6), exact
+ * in single precision.                                                     */
+float or_noise_gauss(uint64_t seed, int64_t frame, int32_t e, int32_t j) {
+    uint64_t st = seed ^ ((uint64_t)frame * 0x9E3779B97F4A7C15ull) ^
+                  ((uint64_t)(uint32_t)e * 0xC2B2AE3D27D4EB4Full) ^
+                  ((uint64_t)(uint32_t)j * 0x165667B19E3779F9ull);
+    int64_t sum = 0;
+    for (int i = 0; i < 3; i++) {
+        uint64_t o = or_splitmix64_next(&st);
+        for (int k = 0; k < 4; k++) sum += (int64_t)((o >> (16 * k)) & 0xFFFFu);
+    }
+    return (float)((double)(sum + 6) / 65536.0 - 6.0);
 }
 
 /* Decision history for the error classes of Sec. II-C.  After every
@@ -618,14 +643,23 @@ static void decode_frames(job_t *jb) {
                 if (pass) { it_done = it; okv = 1; break; }
             }
             if (it == p->max_iter) break;
-            if ((p->pp_mode == 0 || p->pp_mode == 1) && jb->pool_q > 1 && it % p->T == 0) {
+            if ((p->pp_mode == 0 || p->pp_mode == 1) && it % p->T == 0) {
                 int32_t q = (it / p->T) % jb->pool_q;
-                if (q != cur_q) {
+                if (jb->pool_q > 1 && q != cur_q) {
                     int kk = (p->pp_mode == 1) ? n : p->k;
                     set_uniform_order(&sc, N, jb->pool + (size_t)q * n);
                     /* the levels between the re-ordered stages lose meaning */
                     if (kk >= 2) zero_levels(N, L, R, n - kk + 1, n - 1, 0, N);
                     cur_q = q;
+                }
+                if (p->noise_sigma > 0.0f) {
+                    /* fresh channel noise on the received LLRs */
+                    int32_t e = it / p->T;
+                    for (int32_t j = 0; j < N; j++) {
+                        double g = (double)or_noise_gauss(p->seed, f, e, j);
+                        L[j] = rnd(p->fp32, (double)jb->llr[f * N + j] +
+                                                rnd(p->fp32, (double)p->noise_sigma * g));
+                    }
                 }
             } else if (p->pp_mode == 2 && it == next_reset) {
                 int32_t nz = 0;
@@ -687,6 +721,8 @@ static int decode_impl(int32_t N, int32_t K, const int32_t *info_idx, int32_t cr
                             p->P_level > n - 1 || p->N_min < 1))
         return OR_EINVAL;
     if (p->exact_boxplus && p->fp32) return OR_EINVAL;
+    if (!(p->noise_sigma >= 0.0f) || (p->noise_sigma > 0.0f && p->pp_mode != 0 && p->pp_mode != 1))
+        return OR_EINVAL;
     if (F == 0) return OR_OK;
     code_t c = {N, n, K, crc_width, crc_poly, info_idx, NULL};
     c.frozen = (uint8_t *)malloc((size_t)N);
