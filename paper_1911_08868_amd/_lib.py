@@ -44,7 +44,8 @@ class PPParamsC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("period_T", ctypes.c_int32),
                 ("pool_Q", ctypes.c_int32), ("P_range", ctypes.c_int32),
                 ("P_level", ctypes.c_int32), ("D", ctypes.c_int32), ("N_min", ctypes.c_int32),
-                ("first_reset", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("first_reset", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("noise_sigma", ctypes.c_float)]
 
 
 class LaunchCfgC(ctypes.Structure):

@@ -66,10 +66,12 @@ class PPParams:
     N_min: int = 0
     first_reset: int = 0
     seed: int = 0
+    noise_sigma: float = 0.0
 
     def c(self) -> PPParamsC:
         return PPParamsC(self.mode, self.k, self.period_T, self.pool_Q, self.P_range,
-                         self.P_level, self.D, self.N_min, self.first_reset, self.seed)
+                         self.P_level, self.D, self.N_min, self.first_reset, self.seed,
+                         self.noise_sigma)
 
 
 @dataclass

@@ -3,8 +3,8 @@
 Every translation unit is compiled in parallel into ``_build/`` and linked
 in-tree, so the library travels with the source tree.  The decode kernels are
 instantiated once per block length (PBP_NLOG = 1..12) in separate objects,
-and once more per length for the decision-history and the exact-boxplus
-kernel families.
+and once more per length for each of the decision-history, exact-boxplus
+and noise-injection kernel families.
 """
 from __future__ import annotations
 
@@ -41,6 +41,8 @@ def _units():
                       [f"-DPBP_NLOG={n}", "-DPBP_VARIANT=1"]))
         units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_exact_n{n:02d}.o",
                       [f"-DPBP_NLOG={n}", "-DPBP_VARIANT=2"]))
+        units.append((os.path.join(CSRC, "decode_inst.hip"), f"decode_noise_n{n:02d}.o",
+                      [f"-DPBP_NLOG={n}", "-DPBP_VARIANT=3"]))
     for n in range(4, 13):
         units.append((os.path.join(CSRC, "wbp_inst.hip"), f"wbp_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
     for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip", "alg1.hip", "diag.hip"):

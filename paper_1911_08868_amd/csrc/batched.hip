@@ -57,6 +57,7 @@ struct BatchedArgs {
 template <int N_>
 struct BatchSrc {
     static constexpr bool kTrace = false;
+    static constexpr bool kNoise = false;
     const BatchedArgs &a;
     int64_t F;
     int b, count, start;
@@ -206,6 +207,7 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
         return fail(PC_ENOTSUP, "batched decoding uses the CRC test (or none)");
     if (!(bp->alpha > 0.f) || !std::isfinite(bp->alpha)) return fail(PC_EINVAL, "alpha must be finite and > 0");
     if (bp->check != PC_CHECK_MINSUM) return fail(PC_ENOTSUP, "the batched decoder is built for min-sum");
+    if (pp && pp->noise_sigma != 0.f) return fail(PC_ENOTSUP, "the batched decoder injects no noise");
     BatchedArgs a;
     std::memset(&a, 0, sizeof(a));
     for (int i = 0; i < n_codes; ++i) {

@@ -361,6 +361,24 @@ __device__ __forceinline__ uint64_t splitmix64_next(uint64_t &s) {
     return z ^ (z >> 31);
 }
 
+// Noise of the noise-aided schedules: an Irwin-Hall approximation of N(0,1)
+// for (frame, event e, row j): the twelve 16-bit fields k of three SplitMix64
+// outputs from the state seed ^ frame 0x9E3779B97F4A7C15 ^ e 0xC2B2AE3D27D4EB4F
+// ^ j 0x165667B19E3779F9, each read as (k + 1/2) / 2^16, summed, minus 6.
+// The result is a multiple of 2^-16 in (-6, 6), exact in single precision.
+__device__ __forceinline__ float noise_gauss(uint64_t seed, int64_t frame, int e, int j) {
+    uint64_t s = seed ^ ((uint64_t)frame * 0x9E3779B97F4A7C15ull) ^
+                 ((uint64_t)(uint32_t)e * 0xC2B2AE3D27D4EB4Full) ^
+                 ((uint64_t)(uint32_t)j * 0x165667B19E3779F9ull);
+    uint32_t sum = 6;
+    for (int r = 0; r < 3; ++r) {
+        const uint64_t o = splitmix64_next(s);
+        sum += (uint32_t)(o & 0xFFFFu) + (uint32_t)((o >> 16) & 0xFFFFu) + (uint32_t)((o >> 32) & 0xFFFFu) +
+               (uint32_t)(o >> 48);
+    }
+    return (float)sum * (1.0f / 65536.0f) - 6.0f;
+}
+
 // Zobrist key of row j for the decision history (error classes, Sec. II-C):
 // the first SplitMix64 output from state j.  The hash of a decision vector
 // is the xor of the keys of its ones.

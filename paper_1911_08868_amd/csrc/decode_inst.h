@@ -13,14 +13,15 @@ struct DecodeLaunch {
     int kp = 0;
     bool scaled = false, gmode = false;
     // kernel family: 0 min-sum, 1 min-sum with decision history, 2 exact
-    // boxplus (1 and 2 are built with two rows per thread only)
+    // boxplus, 3 min-sum with noise injected at the events (1..3 are built
+    // with two rows per thread only)
     int variant = 0;
     int rho = 2, slots = 0, grid = 0;
     int64_t F = 0;
     hipStream_t stream = nullptr;
 };
 
-template <int NLOG, int KP, int RHO, int CN, bool GM, bool TR>
+template <int NLOG, int KP, int RHO, int CN, bool GM, bool TR, bool NZ>
 int run_decode(const DecodeLaunch &L) {
     using P = Plan<NLOG, KP, RHO>;
     const int TPS = P::TPS;
@@ -30,7 +31,7 @@ int run_decode(const DecodeLaunch &L) {
     if (S * TPS > LB) return fail(PC_EINVAL, "slots * threads per frame exceeds the launch bound");
     const size_t lds = DecodeLds<P>::bytes(S);
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for this launch shape");
-    auto kern = k_decode<NLOG, KP, RHO, CN, GM, TR>;
+    auto kern = k_decode<NLOG, KP, RHO, CN, GM, TR, NZ>;
     int grid = L.grid;
     if (grid <= 0) {
         int per_cu = 0;
@@ -51,10 +52,10 @@ int run_decode(const DecodeLaunch &L) {
 template <int NLOG, int KP, int RHO, int V, bool GM>
 int run_decode_check(const DecodeLaunch &L) {
     if constexpr (V == 2) {
-        return run_decode<NLOG, KP, RHO, 2, GM, false>(L);
+        return run_decode<NLOG, KP, RHO, 2, GM, false, false>(L);
     } else {
-        return L.scaled ? run_decode<NLOG, KP, RHO, 1, GM, V == 1>(L)
-                        : run_decode<NLOG, KP, RHO, 0, GM, V == 1>(L);
+        return L.scaled ? run_decode<NLOG, KP, RHO, 1, GM, V == 1, V == 3>(L)
+                        : run_decode<NLOG, KP, RHO, 0, GM, V == 1, V == 3>(L);
     }
 }
 
@@ -93,7 +94,8 @@ int run_decode_n(const DecodeLaunch &L) {
         if (L.rho == 3) {
             if constexpr (NLOG >= 3 && V == 0) return run_decode_kp<NLOG, 3, V>(L);
             return fail(V ? PC_ENOTSUP : PC_EINVAL,
-                        V ? "decision history and exact boxplus are built for rho 2" : "rho exceeds log2 N");
+                        V ? "decision history, exact boxplus and noise injection are built for rho 2"
+                          : "rho exceeds log2 N");
         }
         if (L.rho != 2) return fail(PC_EINVAL, "rho must be 2 or 3");
         return run_decode_kp<NLOG, 2, V>(L);

@@ -37,6 +37,8 @@ struct DecodeArgs {
     int8_t orders[8][16];
     uint64_t *hist;  // [F][H] decision hashes (trace kernels only)
     int32_t H;
+    float noise_sigma;    // channel noise injected at every event (noise kernels only)
+    uint64_t noise_seed;
 };
 
 template <class P>
@@ -72,13 +74,18 @@ struct DecodeCtl {
     float alpha;
     int32_t T, Q;
     const int8_t *orders;  // [8][16], in global or kernel-argument memory
+    float noise_sigma = 0.f;
+    uint64_t noise_seed = 0;
 };
 
 // The lock-step slot loop.  Src supplies frames: pop() (slot leader only)
 // returns the next frame or a value >= Src::F when the queue is empty;
 // per frame it gives the LLR pointer, the code tables and the output sinks.
 // With Src::kTrace the loop also hashes every iteration's decisions
-// (decision_key) and hands the hash to Src::trace (slot leader only).
+// (decision_key) and hands the hash to Src::trace (slot leader only).  With
+// Src::kNoise every event (after iterations T, 2T, ..., also where the graph
+// stays) sets the channel level to the received LLRs plus
+// noise_sigma * noise_gauss(frame, event, row).
 // tid is the thread's index in the workgroup (threadIdx.x, or a copy the
 // caller has hidden from the optimiser).
 template <int NLOG, int KP, int RHO, int CN, bool GMODE, class Src>
@@ -96,6 +103,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     // and leaves when none of its slots has a frame.
     constexpr bool WSLOT = TPS <= 64;
     constexpr bool TRACE = Src::kTrace;
+    constexpr bool NOISE = Src::kNoise;
 
     const int slot = tid / TPS;
     const int t = tid & (TPS - 1);
@@ -129,7 +137,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
     uint64_t htotal = 0;               // the slot's decision hash (one-wave frames)
     uint32_t ubits = 0;
     uint32_t synv_total = 0;  // the slot's syndrome (one-wave frames)
-    int it = 0, q = 0, next_ev = 0;
+    int it = 0, q = 0, next_ev = 0, ev = 0;
     int frame = 0;  // frame indices fit 31 bits (the host checks F)
     const uint32_t *tsyn = nullptr;
     const int32_t *tmeta = nullptr;
@@ -175,6 +183,7 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         it = 0;
         q = 0;
         next_ev = a.T;
+        ev = 0;
         tsyn = src.syn(frame);
         tmeta = src.meta(frame);
         sfor<0, G>([&](auto g) {
@@ -193,6 +202,20 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
         });
         if constexpr (KP == NLOG) load_channel(q);
         load_top_info(q);
+    };
+    // noise injection at event e: received LLR + sigma g, with the channel
+    // row of each register row as load_channel reads it
+    auto inject_noise = [&](int e) {
+        const float *lsrc = src.llr(frame);
+        const int base = GMap<P, 0>::base(t);
+        const int8_t *eo = ords + q * 16;
+        sfor<0, ROWS>([&](auto i) {
+            const int p = base + GMap<P, 0>::off(i);
+            const int j = (KP == NLOG) ? relabel_to_row(p, eo, n, 0) : p;
+            const float g = noise_gauss(a.noise_seed, frame, e, j);
+            const float z = a.noise_sigma * g;
+            st.Lbot[0][i] = lsrc[j] + z;
+        });
     };
 
     for (;;) {
@@ -429,15 +452,18 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
                 need_new = true;
             } else {
                 it += 1;
-                if constexpr (KP > 0) {
+                if constexpr (KP > 0 || NOISE) {
                     // trellis switch at iterations T, 2T, ...: pool entry (it/T) mod Q
                     if (it == next_ev) {
                         next_ev += a.T;
-                        const int qn = q + 1 == a.Q ? 0 : q + 1;
-                        if (qn != q) {
-                            q = qn;
-                            apply_event();
+                        if constexpr (KP > 0) {
+                            const int qn = q + 1 == a.Q ? 0 : q + 1;
+                            if (qn != q) {
+                                q = qn;
+                                apply_event();
+                            }
                         }
+                        if constexpr (NOISE) inject_noise(++ev);
                     }
                 }
             }
@@ -449,10 +475,11 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 // ---------------------------------------------------------------------------
 // Frame source of a single-code launch: a queue counter over frames 0..F-1.
 // With TR it records the decision hash of iteration it (0-based) of frame f
-// at hist[f][it mod H].
-template <int N_, bool TR>
+// at hist[f][it mod H]; NZ selects the noise-injecting schedule.
+template <int N_, bool TR, bool NZ = false>
 struct SingleSrc {
     static constexpr bool kTrace = TR;
+    static constexpr bool kNoise = NZ;
     const DecodeArgs &a;
     int64_t F;
     __device__ SingleSrc(const DecodeArgs &args) : a(args), F(args.F) {}
@@ -472,14 +499,14 @@ struct SingleSrc {
     }
 };
 
-template <int NLOG, int KP, int RHO, int CN, bool GMODE, bool TRACE>
-__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO, TRACE>()))
+template <int NLOG, int KP, int RHO, int CN, bool GMODE, bool TRACE, bool NOISE>
+__global__ void __launch_bounds__((decode_launch_bound<NLOG, RHO>()), (decode_min_waves<RHO, TRACE || NOISE>()))
 k_decode(DecodeArgs a) {
     extern __shared__ __align__(16) float smem[];
     constexpr int TPS = Plan<NLOG, KP, RHO>::TPS;
     const int S = blockDim.x / TPS;
-    DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0]};
-    SingleSrc<(1 << NLOG), TRACE> src(a);
+    DecodeCtl c{a.max_iter, a.it_min, a.stop, a.alpha, a.T, a.Q, &a.orders[0][0], a.noise_sigma, a.noise_seed};
+    SingleSrc<(1 << NLOG), TRACE, NOISE> src(a);
     decode_loop<NLOG, KP, RHO, CN, GMODE>(src, c, smem, S, (int)threadIdx.x);
 }
 

@@ -309,6 +309,13 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     const int n = code->n;
     const bool exact = bp->check == PC_CHECK_EXACT;
     if (exact && d_hist) return fail(PC_ENOTSUP, "the decision history is built for min-sum");
+    const float sigma = pp ? pp->noise_sigma : 0.f;
+    if (!(sigma >= 0.f) || !std::isfinite(sigma)) return fail(PC_EINVAL, "noise_sigma must be finite and >= 0");
+    if (sigma > 0.f) {
+        if (mode != PC_PP_LASTK && mode != PC_PP_FULL)
+            return fail(PC_EINVAL, "noise is injected at the events of the fixed schedules (LASTK, FULL)");
+        if (exact || d_hist) return fail(PC_ENOTSUP, "noise injection is built for min-sum without history");
+    }
     if (mode == PC_PP_ALG1) {
         if (exact) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for min-sum");
         if (cfg && (cfg->rho || cfg->slots || cfg->grid))
@@ -361,7 +368,9 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     for (int q = 0; q < Q; ++q)
         for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
     L.kp = kp;
-    L.variant = d_hist ? 1 : exact ? 2 : 0;
+    L.variant = d_hist ? 1 : exact ? 2 : sigma > 0.f ? 3 : 0;
+    a.noise_sigma = sigma;
+    a.noise_seed = pp ? pp->seed : 0;
     L.scaled = bp->alpha != 1.0f;
     L.gmode = bp->stop == PC_STOP_G || (bp->stop == PC_STOP_NONE && code->crc_width == 0);
     L.F = F;

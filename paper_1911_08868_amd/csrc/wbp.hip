@@ -125,6 +125,7 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
     int8_t orders[kMaxPool * kMaxLog] = {0};
     int kp = 0, Q = 1, Tev = 1;
     const int n = c->n;
+    if (pp && pp->noise_sigma != 0.f) return fail(PC_ENOTSUP, "weighted BP injects no noise");
     if (pp && pp->mode != PC_PP_NONE) {
         if (pp->mode != PC_PP_LASTK) return fail(PC_ENOTSUP, "weighted BP supports the fixed last-k schedule");
         if (pp->k < 2 || pp->k > n) return fail(PC_EINVAL, "k must satisfy 2 <= k <= n");

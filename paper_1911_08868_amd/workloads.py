@@ -318,12 +318,54 @@ def exact_boxplus(torch, pbp, F=262144, snrs=(1.5, 2.0, 2.5, 3.0, 3.5)):
                         f"{F} frames per Eb/N0 point, max 200 iterations, CRC stop", "points": points}
 
 
+def noise_aided(torch, pbp, F=65536, sigma=0.6):
+    """Noise injected at the trellis events (sigma^2 = 0.36, the noise-aided BP
+    setting of Table I) with and without the last-4 permutations, beside the
+    last-4 schedule and plain BP, on N=1024 codes of rate 1/2 and 0.65 with
+    CRC-24 (K includes the CRC), at most 200 iterations, CRC stop from
+    iteration 3; events every 10 iterations."""
+    import synth
+    out = []
+    for rate, K, snrs in (("1/2", 512, (2.0, 3.0, 3.5)), ("0.65", 666, (2.5, 3.5, 4.0))):
+        code = pbp.Code(1024, K, 24, 0x1864CFB, 2.5)
+        bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
+        lastk = dict(mode=pbp.PP_LASTK, k=4, period_T=10, seed=1)
+        scheds = (("bp", pbp.PPParams()),
+                  ("lastk4", pbp.PPParams(pool_Q=8, **lastk)),
+                  ("lastk4_noise", pbp.PPParams(pool_Q=8, noise_sigma=sigma, **lastk)),
+                  ("noise_only", pbp.PPParams(pool_Q=1, noise_sigma=sigma, **lastk)))
+        for snr in snrs:
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(int(snr * 100) + K)
+            m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+            x = pbp.encode(code, m)
+            llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
+                                       code.K_msg, gen)
+            row = {"rate": rate, "ebn0_db": snr}
+            for name, pp in scheds:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                res = pbp.pp_mt_bp_decode(code, llr, bp, pp)
+                b.record()
+                torch.cuda.synchronize()
+                row[name] = {"fer": (res[0] != m).any(1).double().mean().item(),
+                             "avg_iters": round(res[1].double().mean().item(), 3),
+                             "ms": round(a.elapsed_time(b), 2)}
+            out.append(row)
+            _log(f"noise-aided R={rate} {snr} dB: " + ", ".join(
+                f"{n} fer {row[n]['fer']:.4g}" for n, _ in scheds))
+    return {"workload": f"noise injected at the events (sigma^2 = {sigma * sigma:.2f}), N=1024, CRC-24, "
+                        f"R = 1/2 (K=512) and 0.65 (K=666), {F} frames per point, max 200 iterations, "
+                        f"CRC stop from iteration 3, events every 10 iterations", "points": out}
+
+
 def bench_extras(torch, pbp):
     from .batched import bench_mixed
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
                      ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1),
-                     ("error_classes", error_classes), ("exact_boxplus", exact_boxplus)):
+                     ("error_classes", error_classes), ("exact_boxplus", exact_boxplus),
+                     ("noise_aided", noise_aided)):
         try:
             out[name] = fn(torch, pbp)
         except Exception as e:  # report the failure in the JSON line, keep the rest
