@@ -265,9 +265,33 @@ def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
         _log(f"error classes at {snr} dB: " + ", ".join(
             f"{n}: fc {row[n]['false_converged']} osc {row[n]['oscillation']} unc {row[n]['unconverged']}"
             for n, _ in scheds))
+    # the higher rate of Sec. IV's comparison (R = 0.65, CRC-24), where the
+    # paper expects converged errors to dominate at high SNR
+    code65 = pbp.Code(1024, 666, 24, 0x1864CFB, 2.5)
+    bp65 = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
+    rate065 = []
+    for snr in (3.5, 4.0):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(snr * 100) + 666)
+        m = torch.randint(0, 2, (F, code65.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+        x = pbp.encode(code65, m)
+        llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
+                                   code65.K_msg, gen)
+        row = {"ebn0_db": snr}
+        for name, pp in scheds[:2]:
+            out = pbp.pp_mt_bp_decode_trace(code65, llr, bp65, pp, H)
+            cls, per = pbp.classify_errors(out[0], m, out[2], out[1], out[3])
+            counts = torch.bincount(cls.long(), minlength=4).tolist()
+            row[name] = {k: int(v) for k, v in zip(names, counts)}
+        rate065.append(row)
+        _log(f"error classes R=0.65 at {snr} dB: " + ", ".join(
+            f"{n}: fc {row[n]['false_converged']} osc {row[n]['oscillation']} unc {row[n]['unconverged']}"
+            for n, _ in scheds[:2]))
     return {"workload": f"error classes (Sec. II-C) from the last {H} decision hashes, N=1024 K=496+CRC16, "
                         f"{F} frames per Eb/N0 point, max 200 iterations, CRC stop; plain BP, fixed last-4 "
-                        f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4)", "points": points}
+                        f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4); and N=1024 "
+                        f"K=666 incl. CRC-24 (R=0.65), CRC stop from iteration 3, plain BP and last-4",
+            "points": points, "rate_065": rate065}
 
 
 VALU_PEAK = 256 * 64 * 2.4e9          # non-packed 32-bit VALU lane-slots per second
