@@ -249,8 +249,8 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
  * weights are shared by all trellises (indexed by stage position).
  * d_w float [T_unroll][n][2][N]; d_out_llr float [F][N].  The forward pass
  * writes per-iteration message checkpoints to d_ws, which must hold
- * wbp_workspace_bytes(code, F, T_unroll) bytes and stay untouched until the
- * matching wbp_backward.  d_ws = NULL with ws_bytes = 0 runs the forward pass
+ * wbp_workspace_bytes(code, F, T_unroll) bytes, be 256-byte aligned (as
+ * hipMalloc returns) and stay untouched until the matching wbp_backward.  d_ws = NULL with ws_bytes = 0 runs the forward pass
  * alone (inference): no checkpoints are written and no backward may follow.
  * The last two calls are graph-capturable (kernels only, no memset).       */
 size_t wbp_workspace_bytes(const pc_code *code, int64_t F, int32_t T_unroll);

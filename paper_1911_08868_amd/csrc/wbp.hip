@@ -121,6 +121,8 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
     lay = wbp_layout(c, F, T);
     const bool no_ws = !need_ws && !d_ws && ws_bytes == 0;
     if (F > 0 && !no_ws && (!d_ws || ws_bytes < lay.total)) return fail(PC_ENOMEM, "workspace too small");
+    if (F > 0 && !no_ws && reinterpret_cast<uintptr_t>(d_ws) % 256)
+        return fail(PC_EINVAL, "workspace must be 256-byte aligned");
     std::memset(&L.args, 0, sizeof(L.args));
     int8_t orders[kMaxPool * kMaxLog] = {0};
     int kp = 0, Q = 1, Tev = 1;

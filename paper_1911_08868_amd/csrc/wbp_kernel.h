@@ -453,8 +453,27 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     // them as this workgroup's partial of iteration it.
     // one-wave frames: sum the iteration's staged gradients over the
     // workgroup's frames, in slot order (the last iteration's R weights get 0)
+    // A workgroup launched with the usual slot count whose slots all hold
+    // frames sums its slots in a fixed unrolled order, four consecutive
+    // entries per thread (16-byte LDS reads and global stores); others take
+    // the general loop.  Both add the slots in slot order.
+    constexpr int SC = P::TPS >= 256 ? 1 : 256 / P::TPS;
+    const bool full = S == SC && frame0 + SC <= a.F;
     auto flush_all = [&](int it, bool lastit) {
         float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+        if (full) {
+            for (int i4 = tid; i4 < n * 2 * N / 4; i4 += blockDim.x) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!(lastit && (((4 * i4) / N) & 1))) {
+                    sfor<0, SC>([&](auto sc) {
+                        const float4 w = *reinterpret_cast<const float4 *>(smem + (size_t)sc * PS + 4 * N + 4 * i4);
+                        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+                    });
+                }
+                *reinterpret_cast<float4 *>(part + 4 * i4) = v;
+            }
+            return;
+        }
         for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
             float v = 0.f;
             if (!(lastit && ((idx / N) & 1)))
@@ -467,6 +486,18 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
         constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
         float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N + lo * 2 * N;
         const float *w0 = smem + 4 * N + par * RHO * N;
+        if (full) {
+            for (int i4 = tid; i4 < r * N / 4; i4 += blockDim.x) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                sfor<0, SC>([&](auto sc) {
+                    const float4 w = *reinterpret_cast<const float4 *>(w0 + (size_t)sc * PS + 4 * i4);
+                    v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+                });
+                const int idx = 4 * i4;
+                *reinterpret_cast<float4 *>(part + ((idx / N) * 2 + d) * N + (idx & (N - 1))) = v;
+            }
+            return;
+        }
         for (int idx = tid; idx < r * N; idx += blockDim.x) {
             float v = 0.f;
             for (int s = 0; s < S; ++s)
