@@ -170,3 +170,26 @@ def test_trace_rejects_bad_history_length(pbp):
     for H in (0, 65):
         with pytest.raises((pbp.PolarError, RuntimeError)):
             pbp.pp_mt_bp_decode_trace(code, llr, pbp.BPParams(max_iter=5, stop=2), None, H)
+
+
+def test_trace_and_classify_edge_cases(orc, pbp):
+    # empty batch, one iteration, a ring longer than the decode, and the
+    # classifier's argument checks
+    import torch
+    code = pbp.Code(64, 40, 8, 0x07, 2.5)
+    empty = torch.zeros((0, 64), dtype=torch.float32, device="cuda")
+    m, it, ok, hist = pbp.pp_mt_bp_decode_trace(code, empty, pbp.BPParams(max_iter=5, stop=2), None, 4)
+    assert m.shape == (0, code.K_msg) and hist.shape == (0, 4)
+    cls, per = pbp.classify_errors(m, m.clone(), ok, it, hist)
+    assert cls.numel() == 0
+    oc, msg, llr = _frames(orc, 64, 40, 8, 0x07, 50, 1.0, seed=3)
+    _, _, _, out = _gpu_trace(pbp, oc, llr, 64, dict(max_iter=1, stop=0), None)
+    m, it, ok, hist = _host(out)
+    assert np.all(it == 1) and np.all(hist[:, 1:] == 0)
+    ref, rhist = orc.decode_trace(oc, llr, orc.DecodeParams(max_iter=1, stop=0, fp32=True), 64)
+    assert np.array_equal(hist, rhist)
+    cls, per = _gpu_classes(pbp, out, msg)
+    assert np.all(per == 0)                  # one sample shows no period
+    with pytest.raises(pbp.PolarError):      # ring length beyond 64
+        pbp.classify_errors(out[0], torch.from_numpy(msg).cuda(), out[2], out[1],
+                            torch.zeros((50, 65), dtype=torch.int64, device="cuda"))
