@@ -61,10 +61,11 @@ struct BatchSrc {
     const BatchedArgs &a;
     int64_t F;
     int b, count, start;
+    ChunkClaim<N_> claim;
     __device__ BatchSrc(const BatchedArgs &args, int bucket)
         : a(args), F(args.F), b(bucket), count(args.ctl[bucket]), start(args.ctl[8 + bucket]) {}
     __device__ int64_t pop() {
-        const int idx = atomicAdd(&a.ctl[24 + b], 1);
+        const int64_t idx = claim.take(count, [&](int k) { return (int64_t)atomicAdd(&a.ctl[24 + b], k); });
         return idx < count ? (int64_t)a.list[start + idx] : F;
     }
     __device__ const float *llr(int64_t f) const { return a.llr_pool + a.llr_off[f]; }

@@ -473,6 +473,27 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
 
 // ---------------------------------------------------------------------------
+// Frames claimed from a shared queue counter in chunks of C consecutive
+// frames: below N = 128 a frame finishes so fast that one atomic per frame on
+// one L2 address caps the frame rate (about 1e8 frames/s), so those lengths
+// take C = 256 / N frames per claim; from N = 128 on every frame is its own
+// chunk (larger chunks measured slower there: a longer tail and frames in
+// flight spread further apart).  Each frame is decoded exactly once.
+template <int N_>
+struct ChunkClaim {
+    static constexpr int C = N_ >= 128 ? 1 : 256 / N_;
+    int64_t next = 0, end = 0;
+    template <class Add>
+    __device__ int64_t take(int64_t total, Add &&add) {
+        if (next < end) return next++;
+        const int64_t base = add(C);
+        if (base >= total) return total;
+        next = base + 1;
+        end = base + C < total ? base + C : total;
+        return base;
+    }
+};
+
 // Frame source of a single-code launch: a queue counter over frames 0..F-1.
 // With TR it records the decision hash of iteration it (0-based) of frame f
 // at hist[f][it mod H]; NZ selects the noise-injecting schedule.
@@ -482,8 +503,11 @@ struct SingleSrc {
     static constexpr bool kNoise = NZ;
     const DecodeArgs &a;
     int64_t F;
+    ChunkClaim<N_> claim;
     __device__ SingleSrc(const DecodeArgs &args) : a(args), F(args.F) {}
-    __device__ int64_t pop() { return (int64_t)atomicAdd(a.counter, 1u); }
+    __device__ int64_t pop() {
+        return claim.take(F, [&](int b) { return (int64_t)atomicAdd(a.counter, (unsigned)b); });
+    }
     __device__ const float *llr(int64_t f) const { return a.llr + f * N_; }
     __device__ const uint32_t *syn(int64_t) const { return a.syn; }
     __device__ const int32_t *meta(int64_t) const { return a.meta; }

@@ -375,7 +375,10 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     L.gmode = bp->stop == PC_STOP_G || (bp->stop == PC_STOP_NONE && code->crc_width == 0);
     L.F = F;
     L.stream = hs;
-    L.rho = cfg && cfg->rho ? cfg->rho : (n >= 2 ? 2 : 1);
+    // default shape: two rows per thread, except N = 512 and 4096, where
+    // eight rows per thread measured faster (one-wave frames at 512); the
+    // side kernel families are built for two rows only
+    L.rho = cfg && cfg->rho ? cfg->rho : (L.variant == 0 && (n == 9 || n == 12)) ? 3 : (n >= 2 ? 2 : 1);
     L.slots = cfg ? cfg->slots : 0;
     L.grid = cfg ? cfg->grid : 0;
     return launch_decode_n(n, L);

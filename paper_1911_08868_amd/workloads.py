@@ -383,11 +383,16 @@ def noise_aided(torch, pbp, F=65536, sigma=0.6):
                         f"CRC stop from iteration 3, events every 10 iterations", "points": out}
 
 
-def bench_extras(torch, pbp):
+def batched_mixed(torch, pbp, F=4_000_000):
+    """The mixed-length stream of the batched decoder (F frames in 4 rounds)."""
     from .batched import bench_mixed
+    return bench_mixed(torch, pbp, frames_total=F)
+
+
+def bench_extras(torch, pbp):
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
-                     ("batched_mixed", bench_mixed), ("algorithm1", alg1_table1),
+                     ("batched_mixed", batched_mixed), ("algorithm1", alg1_table1),
                      ("error_classes", error_classes), ("exact_boxplus", exact_boxplus),
                      ("noise_aided", noise_aided)):
         try:
