@@ -85,11 +85,26 @@ __global__ void k_batch_clear(int32_t *ctl) {
     if (threadIdx.x < 32) ctl[threadIdx.x] = 0;
 }
 
+// Bucket of frame f (code length 2^(6+b)), or -1 for a skipped frame.
+__device__ __forceinline__ int frame_bucket(const BatchedArgs &a, int64_t f) {
+    if (f >= a.F) return -1;
+    const int c = a.code_id[f];
+    return (c >= 0 && c < a.n_codes) ? a.codes[c].n - 6 : -1;
+}
+
+// The queue preparation aggregates per wave: one ballot per bucket and one
+// atomic per bucket and wave instead of one per frame (a single address took
+// one atomic per frame of a one-length stream, about 1e8 per second).  Every
+// wave runs the same number of trips, so the ballots see all 64 lanes.
 __global__ void __launch_bounds__(256) k_batch_count(BatchedArgs a) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.F;
-         f += (int64_t)gridDim.x * blockDim.x) {
-        const int c = a.code_id[f];
-        if (c >= 0 && c < a.n_codes) atomicAdd(&a.ctl[a.codes[c].n - 6], 1);  // others are skipped
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t f0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); f0 < a.F; f0 += stride) {
+        const int b = frame_bucket(a, f0 + lane);
+        for (int k = 0; k < kBuckets; ++k) {
+            const uint64_t m = __ballot(b == k);
+            if (lane == 0 && m) atomicAdd(&a.ctl[k], (int)__popcll(m));
+        }
     }
 }
 
@@ -104,14 +119,23 @@ __global__ void k_batch_layout(int32_t *ctl) {
     }
 }
 
+// Each wave reserves, per bucket, one range of the bucket's list for its
+// frames of that bucket and writes them there in lane order.
 __global__ void __launch_bounds__(256) k_batch_scatter(BatchedArgs a) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.F;
-         f += (int64_t)gridDim.x * blockDim.x) {
-        const int c = a.code_id[f];
-        if (c < 0 || c >= a.n_codes) continue;
-        const int b = a.codes[c].n - 6;
-        const int pos = atomicAdd(&a.ctl[16 + b], 1);
-        a.list[pos] = (int32_t)f;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t f0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); f0 < a.F; f0 += stride) {
+        const int64_t f = f0 + lane;
+        const int b = frame_bucket(a, f);
+        for (int k = 0; k < kBuckets; ++k) {
+            const uint64_t m = __ballot(b == k);
+            if (!m) continue;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctl[16 + k], (int)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (b == k) a.list[base + (int)__popcll(m & below)] = (int32_t)f;
+        }
     }
 }
 
