@@ -262,3 +262,37 @@ def test_full_size_n1024_sampled(orc, pbp):
     hi = beta.ppf(0.975, e + 1, 2000 - e)
     assert lo <= fer_gpu <= hi, (fer_gpu, lo, hi)
     del oc_l
+
+
+@pytest.mark.parametrize("N,K,cw,poly,mode", [(256, 144, 16, 0x1021, -1), (1024, 512, 16, 0x1021, 0),
+                                              (64, 40, 8, 0x07, 1)])
+def test_nonfinite_llrs_decode_without_harm(orc, pbp, N, K, cw, poly, mode):
+    # NaN and infinite LLRs give unspecified bits but bounded, well-formed
+    # outputs, and leave the other frames of the batch untouched
+    torch = _torch()
+    oc, msg, llr = frames(orc, N, K, cw, poly, 64, 2.0, seed=17)
+    bad = llr.copy()
+    rng = np.random.default_rng(5)
+    for f in range(0, 64, 2):
+        pos = rng.choice(N, 3, replace=False)
+        bad[f, pos] = [np.nan, np.inf, -np.inf]
+    code = gpu_code(pbp, oc)
+    bp = pbp.BPParams(max_iter=50, stop=pbp.STOP_CRC)
+    pp = pbp.PPParams(mode=mode, k=4 if mode == 0 else 0, period_T=5, pool_Q=8, seed=3)
+    kw = [dict(), dict(cfg=pbp.LaunchCfg(rho=3)) if N >= 8 else dict()]
+    for extra in kw:
+        m, it, ok = pbp.pp_mt_bp_decode(code, torch.from_numpy(bad).cuda(), bp, pp, **extra)
+        m0, it0, ok0 = pbp.pp_mt_bp_decode(code, torch.from_numpy(llr).cuda(), bp, pp, **extra)
+        torch.cuda.synchronize()
+        m, it, ok = m.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy()
+        assert set(np.unique(m)) <= {0, 1} and set(np.unique(ok)) <= {0, 1}
+        assert it.min() >= 1 and it.max() <= 50
+        clean = np.arange(1, 64, 2)
+        assert np.array_equal(m[clean], m0.cpu().numpy()[clean])
+        assert np.array_equal(it[clean], it0.cpu().numpy()[clean])
+    # the side kernel families on the same frames
+    exact = pbp.BPParams(max_iter=50, stop=pbp.STOP_CRC, check=pbp.CHECK_EXACT)
+    out = pbp.pp_mt_bp_decode(code, torch.from_numpy(bad).cuda(), exact, pp)
+    _, _, _, hist = pbp.pp_mt_bp_decode_trace(code, torch.from_numpy(bad).cuda(), bp, pp, 16)
+    torch.cuda.synchronize()
+    assert out[1].cpu().numpy().max() <= 50 and hist.shape == (64, 16)
