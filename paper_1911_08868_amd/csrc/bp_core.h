@@ -199,15 +199,17 @@ __device__ __forceinline__ float log2_1p_exp_neg(float d) {
 
 // Exact boxplus 2 atanh(tanh(x/2) tanh(y/2)) (Sec. II-B) as
 // sgn(x) sgn(y) [min(|x|,|y|) + ln(1 + e^-(|x|+|y|)) - ln(1 + e^-||x|-|y||)],
-// the same function without the saturation of the tanh form.  Equal
-// magnitudes (also +inf against +inf) take the difference 0; a rounding that
-// takes the magnitude below 0 gives 0; +inf against a finite y gives y.  The
-// magnitude's minimum and the clamp use the IEEE-754-2019 minimum/maximum
-// (no NaN can reach them); the last step is one fused multiply-add.
+// the same function without the saturation of the tanh form.  The difference
+// of two infinite magnitudes (NaN) is replaced by the largest float through
+// IEEE minNum (v_min_f32), whose correction term is 0, so +inf against +inf
+// gives +inf as the limit does; +inf against a finite y gives y; a rounding
+// that takes the magnitude below 0 gives 0.  The magnitude's minimum and the
+// clamp use the IEEE-754-2019 minimum/maximum (no NaN reaches them); the last
+// step is one fused multiply-add.
 __device__ __forceinline__ float cnode_exact(float x, float y) {
     const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
     const float m = __builtin_elementwise_minimum(ax, ay);
-    const float d = ax == ay ? 0.f : __builtin_fabsf(ax - ay);
+    const float d = __builtin_fminf(__builtin_fabsf(ax - ay), 3.40282347e38f);
     const float l = log2_1p_exp_neg(ax + ay) - log2_1p_exp_neg(d);
     const float mag = __builtin_elementwise_maximum(__builtin_fmaf(l, 0.693147180559945309f, m), 0.f);
     return __uint_as_float(__float_as_uint(mag) ^ ((__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u));
