@@ -113,17 +113,23 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         __syncthreads();
         return mask;
     };
+    // (called once per iteration, from the decision: the previous reads of
+    // misc[4 + w] are ordered before these writes by the barrier that ends
+    // every R sweep or by the barrier at the top of the frame loop)
     auto wg_xor = [&](uint32_t v) -> uint32_t {
         v = lanes_xor<64>(v);
-        __syncthreads();
         if ((tid & 63) == 0) misc[4 + (tid >> 6)] = (int32_t)v;
         __syncthreads();
-        uint32_t s = 0;
-        for (int w = 0; w < (nt + 63) / 64; ++w) s ^= (uint32_t)misc[4 + w];
-        return s;
+        // lane w of every wave reads wave w's partial: one read and one lane
+        // reduction instead of a read per wave
+        const uint32_t p = lane < nwaves ? (uint32_t)misc[4 + lane] : 0u;
+        return lanes_xor<64>(p);
     };
 
-    // stage s pairs some row with a row of another wave (bit >= 6)
+    // stage s pairs some row with a row of another wave (bit >= 6); the
+    // flags are gathered into a uniform mask (bit s-1) kept in a scalar
+    // register until the next event
+    uint32_t crossm = 0;
     auto update_cross = [&](bool row, int j) {
         __syncthreads();
         if (tid < n) misc[41 + tid] = 0;
@@ -132,6 +138,9 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
             for (int s = 1; s <= n; ++s)
                 if (ord[(s - 1) * N + j] >= 6) misc[40 + s] = 1;
         __syncthreads();
+        uint32_t c = 0;
+        for (int s = 1; s <= n; ++s) c |= (misc[40 + s] != 0 ? 1u : 0u) << (s - 1);
+        crossm = __builtin_amdgcn_readfirstlane(c);
     };
     // the thread's partner (byte offset) and top flag at every stage, cached
     // in registers between events
@@ -146,7 +155,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         });
     };
     auto stage_sync = [&](int s) {
-        if (misc[40 + s]) {
+        if ((crossm >> (s - 1)) & 1u) {
             __syncthreads();
         } else {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
