@@ -159,8 +159,9 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the decode shards by frames and needs no "
-              "collective (see DESIGN.md), but only N=1 is run here", file=sys.stderr)
+        print("bench.py: only --gpus 1 is measured; decoding shards by frame ranges with no "
+              "collective beyond a final count, so more GPUs would each run this same workload",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1911_08868_amd as pbp
