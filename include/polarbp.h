@@ -34,7 +34,7 @@ extern "C" {
 
 #define PC_OK 0
 #define PC_EINVAL (-1)  /* bad argument: null pointer, size or parameter out of range */
-#define PC_ENOTSUP (-2) /* valid combination that this build does not implement       */
+#define PC_ENOTSUP (-2) /* valid combination that this library does not implement     */
 #define PC_EHIP (-3)    /* HIP runtime or launch error                                */
 #define PC_ENOMEM (-4)  /* workspace too small or device allocation failed            */
 

@@ -82,7 +82,7 @@ int run_decode_kp(const DecodeLaunch &L) {
         case 5: if constexpr (NLOG > 5) return run_decode_flags<NLOG, 5, RHO, V>(L); break;
         default: break;
     }
-    return fail(PC_ENOTSUP, "permuted range k must be 2..5 or n in this build");
+    return fail(PC_ENOTSUP, "permuted range k must be 2..5 or n in this library");
 }
 
 // V: kernel family (DecodeLaunch::variant)

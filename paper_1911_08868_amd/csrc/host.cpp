@@ -198,7 +198,7 @@ const char *polar_strerror(int rc) {
     switch (rc) {
         case PC_OK: return "success";
         case PC_EINVAL: return "invalid argument";
-        case PC_ENOTSUP: return "not supported by this build";
+        case PC_ENOTSUP: return "not supported by this library";
         case PC_EHIP: return "HIP runtime error";
         case PC_ENOMEM: return "out of memory or workspace too small";
         default: return "unknown error";

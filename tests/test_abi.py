@@ -38,7 +38,7 @@ def test_strerror():
     L = pbp.lib()
     assert L.polar_strerror(0) == b"success"
     assert L.polar_strerror(-1) == b"invalid argument"
-    assert L.polar_strerror(-2) == b"not supported by this build"
+    assert L.polar_strerror(-2) == b"not supported by this library"
 
 
 @pytest.mark.parametrize("n,k,Q,seed", [(10, 3, 8, 0), (10, 4, 8, 7), (10, 5, 8, 123),
