@@ -168,7 +168,10 @@ int bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_pa
               uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok, void *stream);
 
 /* Partially permuted multi-trellis BP (Algorithm 1 with the fixed schedules
- * of pc_pp_params).  Arguments as bp_decode.                                */
+ * of pc_pp_params).  Arguments as bp_decode.  The decode entry points enqueue
+ * kernels only (the queue counter is reset by a kernel, no memset): after one
+ * warm-up call on the device, a call can be captured into a HIP graph and
+ * replayed with new data in the same buffers.                              */
 int pp_mt_bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
                     const pc_pp_params *pp, uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok,
                     void *stream);
