@@ -234,8 +234,10 @@ int polar_classify_errors(const uint8_t *d_msg_hat, const uint8_t *d_msg, const 
  * its own kernels (no memset), so after one warm-up call on the device the
  * whole call can be captured into a HIP graph and replayed with new frame
  * data in the same buffers.  Overlapping calls must use different workspaces.
- * cfg: rho (2 or 3), slots = 1 (256-thread workgroups) or 2 (512), grid
- * (0 = as many workgroups as fit); NULL for the defaults.                   */
+ * cfg: rho (2 or 3: every length under that rho in one launch; 0: the
+ * 512-bit frames under rho 3 in a launch of their own, then the other lengths
+ * under rho 2), slots = 1 (256-thread workgroups) or 2 (512), grid (0 = as
+ * many workgroups as fit, per launch); NULL for the defaults (rho 0).       */
 size_t polar_batched_workspace_bytes(int64_t F);
 int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
                             const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,

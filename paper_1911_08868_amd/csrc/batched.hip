@@ -154,27 +154,30 @@ __device__ __forceinline__ void run_bucket(const BatchedArgs &a, float *smem) {
     decode_loop<NLOG, KP, RHO, SCALED, false>(src, c, smem, S, tid);
 }
 
-template <int KPQ, int RHO, bool SCALED>
+// MASK selects the buckets (bit b = length 2^(b+6)) this launch decodes, so
+// that one length can run under another rho in a launch of its own.
+template <int KPQ, int RHO, bool SCALED, int MASK>
 __global__ void __launch_bounds__(512, (RHO <= 2 ? 4 : 2)) k_batched(BatchedArgs a) {
     extern __shared__ __align__(16) float smem[];
     for (int b = kBuckets - 1; b >= 0; --b) {
-        if (a.ctl[b] == 0) continue;
+        if (!((MASK >> b) & 1) || a.ctl[b] == 0) continue;
         switch (b) {
-            case 4: run_bucket<10, KPQ, RHO, SCALED>(a, smem); break;
-            case 3: run_bucket<9, KPQ, RHO, SCALED>(a, smem); break;
-            case 2: run_bucket<8, KPQ, RHO, SCALED>(a, smem); break;
-            case 1: run_bucket<7, KPQ, RHO, SCALED>(a, smem); break;
-            default: run_bucket<6, KPQ, RHO, SCALED>(a, smem); break;
+            case 4: if constexpr ((MASK >> 4) & 1) run_bucket<10, KPQ, RHO, SCALED>(a, smem); break;
+            case 3: if constexpr ((MASK >> 3) & 1) run_bucket<9, KPQ, RHO, SCALED>(a, smem); break;
+            case 2: if constexpr ((MASK >> 2) & 1) run_bucket<8, KPQ, RHO, SCALED>(a, smem); break;
+            case 1: if constexpr ((MASK >> 1) & 1) run_bucket<7, KPQ, RHO, SCALED>(a, smem); break;
+            default: if constexpr (MASK & 1) run_bucket<6, KPQ, RHO, SCALED>(a, smem); break;
         }
         __syncthreads();
     }
 }
 
-template <int KPQ, int RHO>
+template <int KPQ, int RHO, int MASK>
 static size_t batched_lds(int block) {
     size_t m = 0;
     auto one = [&](auto P, int n) {
         using PP = decltype(P);
+        if (!((MASK >> (n - 6)) & 1)) return;
         const int S = block / PP::TPS;
         m = std::max(m, DecodeLds<PP>::bytes(S < 1 ? 1 : S));
     };
@@ -186,17 +189,18 @@ static size_t batched_lds(int block) {
     return m;
 }
 
-template <int KPQ, int RHO, bool SC>
+template <int KPQ, int RHO, bool SC, int MASK>
 static int launch_batched_kernel(const BatchedArgs &a, int block, int grid, hipStream_t s) {
-    auto kern = k_batched<KPQ, RHO, SC>;
-    const size_t lds = batched_lds<KPQ, RHO>(block);
+    auto kern = k_batched<KPQ, RHO, SC, MASK>;
+    const size_t lds = batched_lds<KPQ, RHO, MASK>(block);
     if (grid <= 0) {
         // occupancy is a property of the kernel and launch shape: cache it
+        // (one cache per kernel instance)
         static std::mutex mu;
-        static int cached[2][2] = {{0, 0}, {0, 0}};
+        static int cached[2] = {0, 0};
         const int bi = block == 512 ? 1 : 0;
         std::lock_guard<std::mutex> lk(mu);
-        int &per_cu = cached[bi][RHO == 3 ? 1 : 0];
+        int &per_cu = cached[bi];
         if (per_cu == 0) {
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
             if (e != hipSuccess) return hip_fail(e, "occupancy query");
@@ -207,6 +211,19 @@ static int launch_batched_kernel(const BatchedArgs &a, int block, int grid, hipS
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PC_OK : hip_fail(e, "batched decode launch");
+}
+
+// rho 2 or 3 decodes every length in one launch; rho 0 decodes the 512-bit
+// frames under rho 3 in a launch of their own (at n = 9 rho 2 leaves half of
+// each 128-thread slot's lanes to the two-slot lock step) and the other
+// lengths under rho 2 in a second launch on the same stream.
+template <int KPQ, bool SC>
+static int launch_batched_rho(const BatchedArgs &a, int rho, int block, int grid, hipStream_t s) {
+    if (rho == 2) return launch_batched_kernel<KPQ, 2, SC, 0x1f>(a, block, grid, s);
+    if (rho == 3) return launch_batched_kernel<KPQ, 3, SC, 0x1f>(a, block, grid, s);
+    const int r = launch_batched_kernel<KPQ, 3, SC, 0x08>(a, block, grid, s);
+    if (r != PC_OK) return r;
+    return launch_batched_kernel<KPQ, 2, SC, 0x17>(a, block, grid, s);
 }
 
 size_t batched_ws_bytes(int64_t F) { return 256 + (size_t)std::max<int64_t>(F, 1) * sizeof(int32_t); }
@@ -286,10 +303,10 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
     a.it_min = bp->it_min;
     a.stop = bp->stop;
     a.alpha = bp->alpha;
-    const int rho = cfg && cfg->rho ? cfg->rho : 2;
+    const int rho = cfg ? cfg->rho : 0;
     const int block = cfg && cfg->slots == 2 ? 512 : kBatchBlock;
     const int grid = cfg ? cfg->grid : 0;
-    if (rho != 2 && rho != 3) return fail(PC_EINVAL, "rho must be 2 or 3");
+    if (rho != 0 && rho != 2 && rho != 3) return fail(PC_EINVAL, "rho must be 0, 2 or 3");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int prep_grid = (int)std::min<int64_t>((F + 255) / 256, (int64_t)device_cu_count() * 4);
     hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, a.ctl);
@@ -299,16 +316,10 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched queue preparation");
     const bool sc = bp->alpha != 1.0f;
-    if (kq == 4) {
-        if (rho == 2) return sc ? launch_batched_kernel<4, 2, true>(a, block, grid, s)
-                                : launch_batched_kernel<4, 2, false>(a, block, grid, s);
-        return sc ? launch_batched_kernel<4, 3, true>(a, block, grid, s)
-                  : launch_batched_kernel<4, 3, false>(a, block, grid, s);
-    }
-    if (rho == 2) return sc ? launch_batched_kernel<0, 2, true>(a, block, grid, s)
-                            : launch_batched_kernel<0, 2, false>(a, block, grid, s);
-    return sc ? launch_batched_kernel<0, 3, true>(a, block, grid, s)
-              : launch_batched_kernel<0, 3, false>(a, block, grid, s);
+    if (kq == 4) return sc ? launch_batched_rho<4, true>(a, rho, block, grid, s)
+                           : launch_batched_rho<4, false>(a, rho, block, grid, s);
+    return sc ? launch_batched_rho<0, true>(a, rho, block, grid, s)
+              : launch_batched_rho<0, false>(a, rho, block, grid, s);
 }
 
 }  // extern "C"

@@ -115,8 +115,8 @@ def tune_batched(torch, dec, reps: int = 2, path: str = _CACHE, force=False):
         return api.LaunchCfg(*c), cache[dk][key]
     results = []
     saved = dec.cfg
-    for cfg in (api.LaunchCfg(2, 1, 0), api.LaunchCfg(2, 2, 0), api.LaunchCfg(3, 1, 0),
-                api.LaunchCfg(3, 2, 0)):
+    for cfg in (api.LaunchCfg(0, 1, 0), api.LaunchCfg(0, 2, 0), api.LaunchCfg(2, 1, 0),
+                api.LaunchCfg(2, 2, 0), api.LaunchCfg(3, 1, 0), api.LaunchCfg(3, 2, 0)):
         dec.cfg = cfg
         try:
             ms = _time(torch, dec.run, reps)
@@ -124,7 +124,7 @@ def tune_batched(torch, dec, reps: int = 2, path: str = _CACHE, force=False):
             continue
         results.append(((cfg.rho, cfg.slots, cfg.grid), ms))
     dec.cfg = saved
-    best = _pick(results)
+    best = _pick(results, default=(0, 1, 0))
     entry = {"cfg": list(best[0]), "ms": best[1], "all": [[list(c), m] for c, m in results],
              "frames": dec.F}
     cache.setdefault(dk, {})[key] = entry

@@ -88,8 +88,9 @@ def _check(ocodes, cid, bits_off, msgs, ref, dev):
 
 
 @pytest.mark.parametrize("pp_on", [True, False])
-@pytest.mark.parametrize("rho,slots,grid", [(2, 1, 0), (2, 2, 0), (3, 1, 0), (2, 1, 1),
-                                            (2, 1, 3), (3, 2, 5)])
+@pytest.mark.parametrize("rho,slots,grid", [(0, 1, 0), (0, 2, 0), (0, 1, 2), (2, 1, 0),
+                                            (2, 2, 0), (3, 1, 0), (2, 1, 1), (2, 1, 3),
+                                            (3, 2, 5)])
 def test_batched_parity(orc, pbp, pp_on, rho, slots, grid):
     import torch
     ocodes, gcodes, cid, bits_off, msgs, dev = _stream(orc, pbp, 400, seed=rho * 7 + slots + grid)
