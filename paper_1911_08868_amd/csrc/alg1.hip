@@ -13,8 +13,11 @@
 // every graph still encodes x = u G_N); otherwise it is drawn again, at most
 // 64 times.  Rows of different blocks then pair on different bits, so the
 // relabelled, register-resident layout of k_decode does not apply: here every
-// row carries its own order (N x n bytes in LDS) and all L and R levels live
-// in LDS, (2n+1) N floats.
+// row carries its own order (4 bits per stage in registers) and every L and R
+// level that a partner reads lives in LDS, (2n-2) N floats (the channel level
+// and the prior are static per frame, so each row holds its partners' values
+// of those in registers).  At N = 1024 that is 73 KiB, and two frames share a
+// CU.
 //
 // One thread per row (up to 1024 rows).  At each stage a row computes its own
 // output of its processing element (Sec. II-B): with j' the partner of row j,
@@ -29,8 +32,9 @@
 // (in the original graph 6 of n stages pair inside a wave).  Overwrites of
 // values other waves read are ordered by the barriers of the decision (L
 // sweep reads, R levels) and by one barrier after the R sweep (its reads of
-// L levels, rewritten by the next L sweep).  The order table
-// is stage-major, [n][N], so a stage's reads are consecutive bytes.  The
+// L levels, rewritten by the next L sweep or an event's labels).  At an
+// event the chosen block's first row publishes its order, which every row
+// compares with its own.  The
 // random draws come from a SplitMix64 stream per frame (seed + (frame + 1) * golden ratio, as in the
 // CPU reference decoder) that every thread advances identically, so all
 // control decisions are uniform.  The component labels of stages 1..m are
@@ -70,30 +74,35 @@ __device__ __forceinline__ uint32_t draw_below(uint64_t &s, uint32_t m) {
 template <int NLOG>
 struct Alg1Lds {
     static constexpr int N = 1 << NLOG, n = NLOG;
-    static constexpr size_t msg_floats = (size_t)(2 * n + 1) * N;  // L levels 0..n, R levels 1..n
-    static constexpr size_t ord_bytes = ((size_t)N * n + 15) & ~(size_t)15;
-    static constexpr size_t bytes = msg_floats * 4 + ord_bytes + (size_t)N * 4 + 128 * 4;
+    // partners read L levels 1..n-1 and R levels 1..n-1 from LDS; the channel
+    // level and the prior level n are static per frame, so each row keeps its
+    // partner's values of those in registers, and L level n is read only by
+    // its own row
+    static constexpr size_t msg_floats = (size_t)(2 * n - 2) * N;
+    static constexpr size_t bytes = msg_floats * 4 + 128 * 4;
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
+// 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 73 KiB)
 template <int NLOG, bool SCALED>
-__global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
+__global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) {
     constexpr int N = 1 << NLOG, n = NLOG;
-    using Lay = Alg1Lds<NLOG>;
     const int tid = threadIdx.x, nt = blockDim.x;
     extern __shared__ __align__(16) float smem[];
-    float *const Lm = smem;                  // level l at Lm + l N, l = 0..n
-    float *const Rm = smem + (size_t)(n + 1) * N - N;  // level l at Rm + l N, l = 1..n
-    int8_t *const ord = reinterpret_cast<int8_t *>(smem + Lay::msg_floats);  // [n][N]: bit of stage s of row j at (s-1) N + j
-    int32_t *const lab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ord) + Lay::ord_bytes);
+    // L level l (1..n-1) at smem + (l-1) N, R level l (1..n-1) at smem + (n+l-2) N
+    auto Lrow = [&](int l) -> float * { return smem + (size_t)(l - 1) * N; };
+    auto Rrow = [&](int l) -> float * { return smem + (size_t)(n + l - 2) * N; };
+    // component labels of an event; they alias L level 1, which is dead from
+    // the end of an R sweep until the next L sweep rewrites it
+    int32_t *const lab = reinterpret_cast<int32_t *>(smem);
     // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
     // counts, [40 + s] stage s pairs across waves, [64..95] wave partials of
-    // the decision hash (lo, hi)
-    int32_t *const misc = lab + N;
+    // the decision hash (lo, hi), [100..101] the root row's stage bits
+    int32_t *const misc = reinterpret_cast<int32_t *>(smem + Alg1Lds<NLOG>::msg_floats);
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
-    auto Lv = [&](int l, int j) -> float & { return Lm[(size_t)l * N + j]; };
-    auto Rv = [&](int l, int j) -> float & { return Rm[(size_t)l * N + j]; };
+    auto Lv = [&](int l, int j) -> float & { return Lrow(l)[j]; };
+    auto Rv = [&](int l, int j) -> float & { return Rrow(l)[j]; };
 
     // workgroup-wide or / sum of per-thread values (includes the barriers)
     auto wg_or = [&](bool v) -> bool {
@@ -126,33 +135,39 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         return lanes_xor<64>(p);
     };
 
+    // the row's stage order: the bit that stage s pairs on, 4 bits per stage
+    // (stage s at bit 4 (s-1)), held in registers
+    uint64_t ordw = 0;
+    auto obit = [&](uint64_t w, int s) -> int { return (int)((w >> (4 * (s - 1))) & 15u); };
+
     // stage s pairs some row with a row of another wave (bit >= 6); the
     // flags are gathered into a uniform mask (bit s-1) kept in a scalar
     // register until the next event
     uint32_t crossm = 0;
-    auto update_cross = [&](bool row, int j) {
+    auto update_cross = [&](bool row) {
         __syncthreads();
         if (tid < n) misc[41 + tid] = 0;
         __syncthreads();
         if (row)
             for (int s = 1; s <= n; ++s)
-                if (ord[(s - 1) * N + j] >= 6) misc[40 + s] = 1;
+                if (obit(ordw, s) >= 6) misc[40 + s] = 1;
         __syncthreads();
         uint32_t c = 0;
         for (int s = 1; s <= n; ++s) c |= (misc[40 + s] != 0 ? 1u : 0u) << (s - 1);
         crossm = __builtin_amdgcn_readfirstlane(c);
     };
-    // the thread's partner (byte offset) and top flag at every stage, cached
-    // in registers between events
-    int pofs[n];
-    uint32_t topm = 0;
-    auto load_pairs = [&](bool row, int j) {
-        topm = 0;
-        sfor<0, n>([&](auto s0) {
-            const int b = row ? ord[s0 * N + j] : 0;
-            pofs[s0] = 4 * (j ^ (1 << b));
-            topm |= (((j >> b) & 1) == 0 ? 1u : 0u) << s0;
-        });
+    // the thread's partner row at stage s and whether the thread's row is the
+    // top one of the pair, from the order in registers (a few VALU per stage
+    // instead of n partner registers); the partner's channel LLR (stage 1)
+    // and prior (stage n) are cached between events
+    auto partner = [&](int j, int s) -> int { return j ^ (1 << obit(ordw, s)); };
+    auto is_top = [&](int j, int s) -> bool { return ((j >> obit(ordw, s)) & 1) == 0; };
+    float pch = 0.f, ppr = 0.f;
+    auto load_pairs = [&](bool row, int j, const float *src) {
+        if (row) {
+            pch = src[partner(j, 1)];
+            ppr = a.meta[partner(j, n)] == -2 ? inf : 0.f;
+        }
     };
     auto stage_sync = [&](int s) {
         if ((crossm >> (s - 1)) & 1u) {
@@ -163,6 +178,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     };
+    uint64_t ident = 0;
+    for (int s = 1; s <= n; ++s) ident |= (uint64_t)(s - 1) << (4 * (s - 1));
 
     for (;;) {
         __syncthreads();
@@ -178,12 +195,11 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
         // the thread's own row on every level, mirrored in registers
         float Lown[n + 1], Rown[n + 1];
         sfor<0, n + 1>([&](auto l) { Lown[l] = 0.f; Rown[l] = 0.f; });
+        ordw = ident;
         if (row) {
             Lown[0] = src[j];
             Rown[n] = a.meta[j] == -2 ? inf : 0.f;
-            sfor<0, n + 1>([&](auto l) { Lv(l, j) = Lown[l]; });
-            sfor<1, n + 1>([&](auto l) { Rv(l, j) = Rown[l]; });
-            for (int s = 0; s < n; ++s) ord[s * N + j] = (int8_t)s;
+            sfor<1, n>([&](auto l) { Rv(l, j) = 0.f; });
         }
         uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
         int next_reset;
@@ -194,8 +210,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
             const int v = full > a.N_min ? full : a.N_min;
             next_reset = v < a.max_iter / 2 ? v : a.max_iter / 2;
         }
-        update_cross(row, j);
-        load_pairs(row, j);
+        update_cross(row);
+        load_pairs(row, j, src);
         const uint64_t hkey = a.hist ? decision_key(j) : 0ull;
 
         int it_done = a.max_iter;
@@ -206,14 +222,15 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 constexpr int s = sc;
                 stage_sync(s);  // level s-1 and R_s of the partner rows
                 if (row) {
-                    const bool top = (topm >> (s - 1)) & 1u;
+                    const bool top = is_top(j, s);
+                    const int p = partner(j, s);
                     const float A = Lown[s - 1];
-                    const float B = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
-                    const float C = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
+                    const float B = s == 1 ? pch : Lrow(s - 1)[p];
+                    const float C = s == n ? ppr : Rrow(s)[p];
                     // top: f(L[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + L[j]
                     const float c = cnode<SCALED>(top ? A : C, top ? B + C : B, alpha);
                     Lown[s] = top ? c : c + A;
-                    Lv(s, j) = Lown[s];
+                    if (s < n) Lv(s, j) = Lown[s];
                 }
             });
             // ---- decision and CRC syndrome on level n+1 ----
@@ -252,10 +269,11 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 constexpr int s = n - kc;
                 stage_sync(s);  // R_s and level s-1 of the partner rows
                 if (row) {
-                    const bool top = (topm >> (s - 1)) & 1u;
+                    const bool top = is_top(j, s);
+                    const int p = partner(j, s);
                     const float P = Rown[s];
-                    const float Q = byte_at(Lm + (size_t)(s - 1) * N, pofs[s - 1]);
-                    const float S = byte_at(Rm + (size_t)s * N, pofs[s - 1]);
+                    const float Q = Lrow(s - 1)[p];
+                    const float S = s == n ? ppr : Rrow(s)[p];
                     // top: f(R[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + R[j]
                     const float c = cnode<SCALED>(top ? P : S, top ? Q + S : Q, alpha);
                     Rown[s - 1] = top ? c : c + P;
@@ -263,7 +281,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 }
             });
             // the R sweep read partners' L messages, which the next L sweep
-            // overwrites; the decision's barriers order the other hazards
+            // (or an event's labels) overwrites; the decision's barriers order
+            // the other hazards
             __syncthreads();
             // ---- partial permutation of one subgraph (Alg. 1 partialPermute) ----
             if (it == next_reset) {
@@ -276,6 +295,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                     const int nblocks = N >> m;
                     const int blk = (int)draw_below(st, (uint32_t)nblocks);
                     // components of stages 1..m: smallest row index by propagation
+                    // (the previous attempt's reads of the labels end at its
+                    // barriers)
                     if (row) lab[j] = j;
                     bool changed = true;
                     while (changed) {
@@ -284,7 +305,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                         if (row) {
                             int v = lab[j];
                             for (int s = 1; s <= m; ++s) {
-                                const int w = lab[j ^ (1 << ord[(s - 1) * N + j])];
+                                const int w = lab[partner(j, s)];
                                 v = w < v ? w : v;
                             }
                             if (v < lab[j]) {
@@ -303,14 +324,19 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                         if (w < wave) before += misc[20 + w];
                     }
                     if (total != nblocks) continue;
-                    if (is_root && before + __popcll(rmask & ((1ull << lane) - 1)) == blk) misc[3] = j;
+                    if (is_root && before + __popcll(rmask & ((1ull << lane) - 1)) == blk) {
+                        misc[3] = j;
+                        misc[100] = (int32_t)(uint32_t)ordw;
+                        misc[101] = (int32_t)(uint32_t)(ordw >> 32);
+                    }
                     __syncthreads();
                     const int root = misc[3];
+                    const uint64_t rord = (uint64_t)(uint32_t)misc[100] | ((uint64_t)(uint32_t)misc[101] << 32);
                     // size of the block and one bit per permuted stage over it
                     const bool member = row && lab[j] == root;
                     bool mixed = false;
                     if (member)
-                        for (int s = rl; s <= m; ++s) mixed |= ord[(s - 1) * N + j] != ord[(s - 1) * N + root];
+                        for (int s = rl; s <= m; ++s) mixed |= obit(ordw, s) != obit(rord, s);
                     wave_counts(member);
                     int members = 0;
                     for (int w = 0; w < nwaves; ++w) members += misc[20 + w];
@@ -318,9 +344,9 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                     if (bad || members != (1 << m)) continue;
                     // a new non-identity order of the bits of stages rl..m
                     int8_t bits[kMaxLog], cand[kMaxLog];
-                    for (int i = 0; i < rr; ++i) bits[i] = ord[(rl - 1 + i) * N + root];
-                    bool ident = true;
-                    while (ident) {
+                    for (int i = 0; i < rr; ++i) bits[i] = (int8_t)obit(rord, rl + i);
+                    bool same = true;
+                    while (same) {
                         for (int i = 0; i < rr; ++i) cand[i] = bits[i];
                         for (int i = rr - 1; i >= 1; --i) {
                             const int jj = (int)draw_below(st, (uint32_t)(i + 1));
@@ -328,18 +354,22 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                             cand[i] = cand[jj];
                             cand[jj] = tt;
                         }
-                        ident = true;
-                        for (int i = 0; i < rr; ++i) ident &= cand[i] == bits[i];
+                        same = true;
+                        for (int i = 0; i < rr; ++i) same &= cand[i] == bits[i];
                     }
-                    __syncthreads();  // every thread has read the old orders of the root
                     if (member) {
-                        for (int i = 0; i < rr; ++i) ord[(rl - 1 + i) * N + j] = cand[i];
-                        // levels strictly between the permuted stages (Sec. III)
+                        for (int i = 0; i < rr; ++i) {
+                            const int sh = 4 * (rl - 1 + i);
+                            ordw = (ordw & ~(15ull << sh)) | ((uint64_t)(uint8_t)cand[i] << sh);
+                        }
+                        // levels strictly between the permuted stages (Sec. III);
+                        // L levels are rewritten by the next L sweep before any
+                        // read, so only the registers and the R levels in LDS
+                        // are cleared
                         sfor<1, n>([&](auto l) {
                             if (l >= rl && l <= m - 1) {
                                 Lown[l] = 0.f;
                                 Rown[l] = 0.f;
-                                Lv(l, j) = 0.f;
                                 Rv(l, j) = 0.f;
                             }
                         });
@@ -350,8 +380,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads) k_alg1(Alg1Args a) {
                 int add = a.D > 0 ? n_zero / a.D : 0;
                 if (add < a.N_min) add = a.N_min;
                 next_reset = it + add;
-                update_cross(row, j);
-                load_pairs(row, j);
+                update_cross(row);
+                load_pairs(row, j, src);
             }
         }
 
