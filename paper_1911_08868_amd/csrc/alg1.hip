@@ -156,21 +156,35 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
         for (int s = 1; s <= n; ++s) c |= (misc[40 + s] != 0 ? 1u : 0u) << (s - 1);
         crossm = __builtin_amdgcn_readfirstlane(c);
     };
-    // the thread's partner row at stage s and whether the thread's row is the
-    // top one of the pair, from the order in registers (a few VALU per stage
-    // instead of n partner registers); the partner's channel LLR (stage 1)
-    // and prior (stage n) are cached between events
+    // the thread's partner row at stage s, from the order in registers
     auto partner = [&](int j, int s) -> int { return j ^ (1 << obit(ordw, s)); };
-    auto is_top = [&](int j, int s) -> bool { return ((j >> obit(ordw, s)) & 1) == 0; };
+    // between events the partner rows are cached, 10 bits per stage and three
+    // stages per register; a row is the top one of its pair iff its partner
+    // is the larger index.  The partner's channel LLR (stage 1) and prior
+    // (stage n) are cached too.
+    constexpr int kPk = (n + 2) / 3;
+    uint32_t pk[kPk];
+    sfor<0, kPk>([&](auto i) { pk[i] = 0u; });
+    auto cpart = [&](int s) -> int { return (int)((pk[(s - 1) / 3] >> (10 * ((s - 1) % 3))) & 1023u); };
     float pch = 0.f, ppr = 0.f;
     auto load_pairs = [&](bool row, int j, const float *src) {
+        sfor<0, kPk>([&](auto i) { pk[i] = 0u; });
+        sfor<1, n + 1>([&](auto s) {
+            const uint32_t p = row ? (uint32_t)partner(j, s) : 0u;
+            pk[(s - 1) / 3] |= p << (10 * ((s - 1) % 3));
+        });
         if (row) {
             pch = src[partner(j, 1)];
             ppr = a.meta[partner(j, n)] == -2 ? inf : 0.f;
         }
     };
     auto stage_sync = [&](int s) {
-        if ((crossm >> (s - 1)) & 1u) {
+        // the mask goes through an empty asm at every test, so that the
+        // compiler does not precompute all 2n tests as lane masks and spill
+        // them to VGPR lanes
+        uint32_t cm = crossm;
+        asm volatile("" : "+s"(cm));
+        if ((cm >> (s - 1)) & 1u) {
             __syncthreads();
         } else {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -191,7 +205,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
         // ---- initialise L and R (Alg. 1 initializeLandR) and the orders ----
         const float *src = a.llr + frame * N;
         const int j = tid;
-        const bool row = j < N;
+        // the launch has N threads when N >= 64, so every thread owns a row
+        const bool row = N >= 64 || j < N;
         // the thread's own row on every level, mirrored in registers
         float Lown[n + 1], Rown[n + 1];
         sfor<0, n + 1>([&](auto l) { Lown[l] = 0.f; Rown[l] = 0.f; });
@@ -222,8 +237,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                 constexpr int s = sc;
                 stage_sync(s);  // level s-1 and R_s of the partner rows
                 if (row) {
-                    const bool top = is_top(j, s);
-                    const int p = partner(j, s);
+                    const int p = cpart(s);
+                    const bool top = p > j;
                     const float A = Lown[s - 1];
                     const float B = s == 1 ? pch : Lrow(s - 1)[p];
                     const float C = s == n ? ppr : Rrow(s)[p];
@@ -269,8 +284,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                 constexpr int s = n - kc;
                 stage_sync(s);  // R_s and level s-1 of the partner rows
                 if (row) {
-                    const bool top = is_top(j, s);
-                    const int p = partner(j, s);
+                    const int p = cpart(s);
+                    const bool top = p > j;
                     const float P = Rown[s];
                     const float Q = Lrow(s - 1)[p];
                     const float S = s == n ? ppr : Rrow(s)[p];
