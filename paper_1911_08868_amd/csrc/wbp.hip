@@ -89,15 +89,16 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WbpLayout {
     size_t ckpt_bytes = 0, partial_bytes = 0, mid_bytes = 0, scratch_bytes = 0, total = 0;
-    int slots = 0;
+    int slots = 0, bslots = 0;
     int64_t groups = 0, nchunks = 0;
 };
 
 static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
     WbpLayout w;
     w.slots = wbp_slots(c->n);
+    w.bslots = wbp_bwd_slots_n(c->n);
     const bool big = c->n >= kWbpBigLog;
-    w.groups = big ? std::min<int64_t>(F, wbp_big_grid(c->n)) : (F + w.slots - 1) / w.slots;
+    w.groups = big ? std::min<int64_t>(F, wbp_big_grid(c->n)) : (F + w.bslots - 1) / w.bslots;
     w.ckpt_bytes = align256((size_t)F * (size_t)(T > 1 ? T - 1 : 0) * (size_t)(c->n - 1) * c->N * sizeof(float));
     const size_t len = (size_t)T * c->n * 2 * (size_t)c->N;
     w.partial_bytes = align256((size_t)w.groups * len * sizeof(float));
@@ -159,6 +160,7 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
         for (int s = 0; s < n; ++s) a.orders[q][s] = orders[q * n + s];
     L.kp = kp;
     L.slots = lay.slots;
+    L.bslots = lay.bslots;
     // the forward takes one workgroup per `slots` frames; the adjoint one per
     // partial (the persistent grid for large frames)
     L.grid = (int)((F + lay.slots - 1) / lay.slots);

@@ -10,14 +10,19 @@ struct WbpLaunch {
     WbpArgs args;
     int kp = 0;
     bool backward = false;
-    int slots = 0, grid = 0, bgrid = 0;
+    int slots = 0, bslots = 0, grid = 0, bgrid = 0;
     hipStream_t stream = nullptr;
 };
 
-// frames per workgroup of the weighted kernels for block length 2^n
+// frames per workgroup of the weighted forward for block length 2^n
 inline int wbp_slots(int n) {
     const int tps = 1 << (n - 2);
     return tps >= 256 ? 1 : 256 / tps;
+}
+// and of the adjoint (wbp_bwd_slots in wbp_kernel.h, two rows per thread)
+inline int wbp_bwd_slots_n(int n) {
+    const int tps = 1 << (n - 2);
+    return tps <= 64 ? 512 / tps : wbp_slots(n);
 }
 
 // Block lengths from 2^kWbpBigLog on run the adjoint with its arrays in a
@@ -31,7 +36,9 @@ size_t wbp_big_scratch_floats(int n);
 template <int NLOG, int KP>
 int run_wbp(const WbpLaunch &L) {
     using P = Plan<NLOG, KP, 2>;
-    const int S = L.slots;
+    const int S = L.backward ? L.bslots : L.slots;
+    if (L.backward && NLOG < kWbpBigLog && S != wbp_bwd_slots<NLOG, 2>())
+        return fail(PC_EINVAL, "adjoint slot count does not match the kernel");
     const size_t lds = L.backward && NLOG < kWbpBigLog ? WbpLds<P, true>::bytes(S) : WbpLds<P, false>::bytes(S);
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for weighted BP");
     if (L.backward) {

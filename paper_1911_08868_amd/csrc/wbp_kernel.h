@@ -80,6 +80,22 @@ constexpr int wbp_launch_bound() {
     return ((1 << (NLOG - RHO)) > 256) ? (1 << (NLOG - RHO)) : 256;
 }
 
+// Frames per workgroup of the adjoint.  Every workgroup writes one
+// weight-gradient partial of T n 2 N floats, so one-wave frames take 512
+// threads: half as many partials to write and sum as with 256, at the same
+// waves per CU (the LDS of one such workgroup fills the CU).  Longer frames
+// take as many slots as the forward.
+template <int NLOG, int RHO>
+constexpr int wbp_bwd_slots() {
+    constexpr int tps = 1 << (NLOG - RHO);
+    return tps <= 64 ? 512 / tps : (tps >= 256 ? 1 : 256 / tps);
+}
+template <int NLOG, int RHO>
+constexpr int wbp_bwd_launch_bound() {
+    constexpr int w = (1 << (NLOG - RHO)) * wbp_bwd_slots<NLOG, RHO>();
+    return w > 256 ? w : 256;
+}
+
 // Checkpoint layout of the persistent R state of one frame and iteration:
 // one block per group, in group order; inside group g's block each thread's
 // gsize(g) values (the interior levels, then the top level, in register
@@ -416,7 +432,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
 }
 
 template <int NLOG, int KP, int RHO>
-__global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(WbpArgs a) {
+__global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd(WbpArgs a) {
     using P = Plan<NLOG, KP, RHO>;
     constexpr int N = P::N, ROWS = P::ROWS, TPS = P::TPS, G = P::G, n = NLOG, GB = P::GB;
     constexpr bool MAPPED = (KP > 0 && KP < NLOG);
@@ -457,7 +473,7 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_bwd(Wbp
     // frames sums its slots in a fixed unrolled order, four consecutive
     // entries per thread (16-byte LDS reads and global stores); others take
     // the general loop.  Both add the slots in slot order.
-    constexpr int SC = P::TPS >= 256 ? 1 : 256 / P::TPS;
+    constexpr int SC = wbp_bwd_slots<NLOG, RHO>();
     const bool full = S == SC && frame0 + SC <= a.F;
     auto flush_all = [&](int it, bool lastit) {
         float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
