@@ -72,11 +72,13 @@ def bce_on_information_bits(out_llr, u_info_bits, info_idx):
     """Mean binary cross entropy of the output LLRs at the information rows.
 
     LLR > 0 favours bit 0, so P(bit = 1) = sigmoid(-LLR) and the loss of a row
-    is u softplus(o) + (1 - u) softplus(-o).
+    is u softplus(o) + (1 - u) softplus(-o): the binary cross entropy of
+    logit o against the target 1 - u, which torch evaluates in one fused
+    kernel each way.
     """
     # a gather, whose adjoint is a scatter-add; advanced indexing would
     # adjoin through index_put with accumulation, which sorts the indices
     idx = info_idx.view(1, -1).expand(out_llr.shape[0], -1)
     o = torch.gather(out_llr, 1, idx)
-    u = u_info_bits.to(o.dtype)
-    return (u * torch.nn.functional.softplus(o) + (1 - u) * torch.nn.functional.softplus(-o)).mean()
+    target = 1 - u_info_bits.to(o.dtype)
+    return torch.nn.functional.binary_cross_entropy_with_logits(o, target)

@@ -53,7 +53,7 @@ def weighted_bp(torch, pbp, steps=5, warmup=2, F=16384, T=10):
     def step():
         out = dec(llr)
         loss = bce_on_information_bits(out, u_info, info)
-        opt.zero_grad(set_to_none=False)
+        opt.zero_grad()
         loss.backward()
         opt.step()
         return loss
@@ -130,7 +130,7 @@ def weighted_bp_large(torch, pbp, F_train=1024, F_dec=8192, T=20, steps=2, warmu
     def step():
         out = dec(xt)
         loss = bce_on_information_bits(out, ut, info)
-        opt.zero_grad(set_to_none=False)
+        opt.zero_grad()
         loss.backward()
         # Over 20 unrolled min-sum iterations the gradient of the earliest
         # iterations' weights can explode (every message fans out into later
