@@ -79,7 +79,8 @@ struct Alg1Lds {
     // partner's values of those in registers, and L level n is read only by
     // its own row
     static constexpr size_t msg_floats = (size_t)(2 * n - 2) * N;
-    static constexpr size_t bytes = msg_floats * 4 + 128 * 4;
+    // + 192 control words + the rows' syndrome columns (read at every decision)
+    static constexpr size_t bytes = msg_floats * 4 + 192 * 4 + (size_t)N * 4;
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
@@ -97,24 +98,38 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
     int32_t *const lab = reinterpret_cast<int32_t *>(smem);
     // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
     // counts, [40 + s] stage s pairs across waves, [64..95] wave partials of
-    // the decision hash (lo, hi), [100..101] the root row's stage bits
+    // the decision hash (lo, hi), [100..101] the root row's stage bits,
+    // [128..159] per-wave flags of the label passes (two sets, by pass
+    // parity), [160..175] per-wave flags of the block check
     int32_t *const misc = reinterpret_cast<int32_t *>(smem + Alg1Lds<NLOG>::msg_floats);
+    uint32_t *const synl = reinterpret_cast<uint32_t *>(misc + 192);
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
     auto Lv = [&](int l, int j) -> float & { return Lrow(l)[j]; };
     auto Rv = [&](int l, int j) -> float & { return Rrow(l)[j]; };
 
-    // workgroup-wide or / sum of per-thread values (includes the barriers)
-    auto wg_or = [&](bool v) -> bool {
+    const int wave = tid >> 6, nwaves = (nt + 63) >> 6, lane = tid & 63;
+    // workgroup-wide or of a per-thread predicate with one barrier: each wave
+    // publishes its ballot in misc[base + w] and every lane w reads wave w's.
+    // The caller alternates base between calls whose flags could still be
+    // read (the barrier of the next call orders those reads before reuse).
+    auto wg_any = [&](bool v, int base) -> bool {
+        const bool w = __ballot(v) != 0;
+        if (lane == 0) misc[base + wave] = w ? 1 : 0;
         __syncthreads();
-        if (tid == 0) misc[1] = 0;
-        __syncthreads();
-        if (v) misc[1] = 1;
-        __syncthreads();
-        return misc[1] != 0;
+        const int f = lane < nwaves ? misc[base + lane] : 0;
+        return __ballot(f != 0) != 0;
+    };
+    // sum of lanes 0..15 of v as a uniform value (called with every lane
+    // active, so lane 0 holds the sum)
+    auto sum16 = [&](int v) -> int {
+        v += __shfl_xor(v, 1, 16);
+        v += __shfl_xor(v, 2, 16);
+        v += __shfl_xor(v, 4, 16);
+        v += __shfl_xor(v, 8, 16);
+        return __builtin_amdgcn_readlane(v, 0);
     };
     // per-wave population counts of a predicate, published in misc[20 + w]
-    const int wave = tid >> 6, nwaves = (nt + 63) >> 6, lane = tid & 63;
     auto wave_counts = [&](bool v) -> uint64_t {
         const uint64_t mask = __ballot(v);
         __syncthreads();
@@ -215,6 +230,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
             Lown[0] = src[j];
             Rown[n] = a.meta[j] == -2 ? inf : 0.f;
             sfor<1, n>([&](auto l) { Rv(l, j) = 0.f; });
+            synl[j] = a.syn[j];  // read back by this thread only
         }
         uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
         int next_reset;
@@ -251,7 +267,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
             // ---- decision and CRC syndrome on level n+1 ----
             uint32_t syn = 0;
             const bool one = row && Lown[n] + Rown[n] < 0.f;
-            if (one) syn = a.syn[j];
+            if (one) syn = synl[j];
             if (a.hist) {
                 // decision hash of this iteration (error classes, Sec. II-C);
                 // the partials are read after wg_xor's barriers and rewritten
@@ -309,35 +325,41 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const int m = rl + rr - 1;
                     const int nblocks = N >> m;
                     const int blk = (int)draw_below(st, (uint32_t)nblocks);
-                    // components of stages 1..m: smallest row index by propagation
-                    // (the previous attempt's reads of the labels end at its
-                    // barriers)
+                    // components of stages 1..m: smallest row index.  Sweeps over
+                    // stages 1..m replace each row's label with the smaller of its
+                    // own and its stage partner's, ordered like the decoding
+                    // sweeps (a workgroup barrier only before a stage that pairs
+                    // across waves).  Both rows of a pair end with the pair's
+                    // minimum whichever order their accesses take.  Labels stay
+                    // rows of the same component, at most the row itself; a sweep
+                    // that changes nothing leaves them equal across every pair,
+                    // so each component holds its smallest row.  On an unpermuted
+                    // block one sweep reaches the minimum (a butterfly), the next
+                    // confirms it.  (The previous attempt's reads of the labels
+                    // end at its barriers.)
+                    int lj = j;
                     if (row) lab[j] = j;
-                    bool changed = true;
-                    while (changed) {
+                    __syncthreads();
+                    for (int sweep = 0;; ++sweep) {
                         bool c = false;
-                        __syncthreads();
-                        if (row) {
-                            int v = lab[j];
-                            for (int s = 1; s <= m; ++s) {
+                        for (int s = 1; s <= m; ++s) {
+                            if (s > 1) stage_sync(s);
+                            if (row) {
                                 const int w = lab[partner(j, s)];
-                                v = w < v ? w : v;
-                            }
-                            if (v < lab[j]) {
-                                lab[j] = v;
-                                c = true;
+                                if (w < lj) {
+                                    lj = w;
+                                    lab[j] = w;
+                                    c = true;
+                                }
                             }
                         }
-                        changed = wg_or(c);
+                        if (!wg_any(c, 128 + 16 * (sweep & 1))) break;
                     }
                     // components (their smallest rows) and the one of rank blk
-                    const bool is_root = row && lab[j] == j;
+                    const bool is_root = row && lj == j;
                     const uint64_t rmask = wave_counts(is_root);
-                    int before = 0, total = 0;
-                    for (int w = 0; w < nwaves; ++w) {
-                        total += misc[20 + w];
-                        if (w < wave) before += misc[20 + w];
-                    }
+                    const int cnt = lane < nwaves ? misc[20 + lane] : 0;
+                    const int total = sum16(cnt), before = sum16(lane < wave ? cnt : 0);
                     if (total != nblocks) continue;
                     if (is_root && before + __popcll(rmask & ((1ull << lane) - 1)) == blk) {
                         misc[3] = j;
@@ -348,14 +370,13 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const int root = misc[3];
                     const uint64_t rord = (uint64_t)(uint32_t)misc[100] | ((uint64_t)(uint32_t)misc[101] << 32);
                     // size of the block and one bit per permuted stage over it
-                    const bool member = row && lab[j] == root;
+                    const bool member = row && lj == root;
                     bool mixed = false;
                     if (member)
                         for (int s = rl; s <= m; ++s) mixed |= obit(ordw, s) != obit(rord, s);
                     wave_counts(member);
-                    int members = 0;
-                    for (int w = 0; w < nwaves; ++w) members += misc[20 + w];
-                    const bool bad = wg_or(mixed);
+                    const int members = sum16(lane < nwaves ? misc[20 + lane] : 0);
+                    const bool bad = wg_any(mixed, 160);
                     if (bad || members != (1 << m)) continue;
                     // a new non-identity order of the bits of stages rl..m
                     int8_t bits[kMaxLog], cand[kMaxLog];

@@ -220,6 +220,53 @@ def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
                         f"max 200 iterations, CRC stop", "points": points}
 
 
+def alg1_long(torch, pbp, F=8192, snrs=(2.0, 2.5, 3.0)):
+    """Algorithm 1 with Table I's 2e4-iteration sets at their full budget:
+    N=1024 R=1/2 (P_range 10, P_level 9, D 100, N_min 15) and N=512 R=0.65
+    (K=333 with CRC-24; P_range 9, P_level 8, D 50, N_min 15), beside plain
+    BP with the same budget on the same frames."""
+    import synth
+    sets = (("N1024_R0.5", 1024, 512, dict(P_range=10, P_level=9, D=100, N_min=15)),
+            ("N512_R0.65", 512, 333, dict(P_range=9, P_level=8, D=50, N_min=15)))
+    bp = pbp.BPParams(max_iter=20000, stop=pbp.STOP_CRC, it_min=3)
+    out = {}
+    for name, N, K, t in sets:
+        code = pbp.Code(N, K, 24, 0x1864CFB, 2.5)
+        alg1 = pbp.PPParams(mode=pbp.PP_ALG1, seed=1, **t)
+        # first launch of this length's kernels, outside the timed calls
+        warm = torch.zeros((64, N), dtype=torch.float32, device="cuda")
+        pbp.pp_mt_bp_decode(code, warm, pbp.BPParams(max_iter=5, stop=pbp.STOP_CRC), alg1)
+        pbp.bp_decode(code, warm, pbp.BPParams(max_iter=5, stop=pbp.STOP_CRC))
+        points = []
+        for snr in snrs:
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(int(snr * 100) + N)
+            m = torch.randint(0, 2, (F, code.K_msg), generator=gen, device="cuda", dtype=torch.uint8)
+            llr = synth.awgn_llr_torch(pbp.encode(code, m), torch.full((F,), snr, device="cuda",
+                                                                       dtype=torch.float64), code.K_msg, gen)
+            row = {"ebn0_db": snr}
+            for dec, run in (("alg1", lambda: pbp.pp_mt_bp_decode(code, llr, bp, alg1)),
+                             ("bp", lambda: pbp.bp_decode(code, llr, bp))):
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                res = run()
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b)
+                it = res[1].double()
+                row[dec] = {"ms": round(ms, 2), "avg_iters": round(it.mean().item(), 2),
+                            "max_iters": int(it.max().item()),
+                            "frame_it_s": round(it.sum().item() / (ms / 1e3)),
+                            "fer": (res[0] != m).any(1).double().mean().item()}
+            points.append(row)
+            _log(f"Algorithm 1 {name} 2e4 set at {snr} dB: fer {row['alg1']['fer']:.4g} "
+                 f"({row['alg1']['ms']} ms) vs BP fer {row['bp']['fer']:.4g} ({row['bp']['ms']} ms)")
+        out[name] = points
+    return {"workload": f"Algorithm 1 with Table I's 2e4-iteration sets vs plain BP, N_it,max = 20000, "
+                        f"CRC-24, CRC stop from iteration 3, {F} frames per Eb/N0 point", "sets": out}
+
+
 def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
     """Error classes of Sec. II-C (false converged / oscillation /
     unconverged) for plain BP, the fixed last-4 schedule and Algorithm 1 on
@@ -393,6 +440,7 @@ def bench_extras(torch, pbp):
     out = {}
     for name, fn in (("weighted_bp", weighted_bp), ("weighted_bp_n4096", weighted_bp_large),
                      ("batched_mixed", batched_mixed), ("algorithm1", alg1_table1),
+                     ("algorithm1_2e4", alg1_long),
                      ("error_classes", error_classes), ("exact_boxplus", exact_boxplus),
                      ("noise_aided", noise_aided)):
         try:
