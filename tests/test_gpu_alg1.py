@@ -78,6 +78,20 @@ def test_table1_n512_rate_065(orc, pbp):
     _assert_parity(got, ref, "Table I N=512 R=0.65")
 
 
+@pytest.mark.parametrize("set_name,N,K", [("N1024_Nitmax20000", 1024, 512),
+                                          ("N512_Nitmax20000", 512, 333)])
+def test_table1_long_budget_many_events(orc, pbp, set_name, N, K):
+    # frames that do not converge within 3000 iterations go through well over
+    # a hundred events each, where valid blocks get rare and most events redraw
+    # several times: the component labels, the block test and the draws after
+    # many permutations
+    t = TABLE1[set_name]
+    got, ref, _ = _run(orc, pbp, N, K, 24, 0x1864CFB, 8, 0.5, 24 + N, 3000, orc.STOP_CRC, 3,
+                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+    _assert_parity(got, ref, f"Table I {set_name}, 3000 iterations")
+    assert (ref.iters == 3000).sum() >= 4
+
+
 @pytest.mark.parametrize("N,K,P_range,P_level,D,N_min,first_reset,alpha", [
     (64, 40, 4, 3, 2, 2, 0, 0.9375),     # scaled min-sum, frequent events
     (128, 80, 7, 6, 0, 3, 5, 1.0),       # D = 0 (spacing N_min), explicit first event
