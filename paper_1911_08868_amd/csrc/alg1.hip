@@ -93,9 +93,11 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
     // L level l (1..n-1) at smem + (l-1) N, R level l (1..n-1) at smem + (n+l-2) N
     auto Lrow = [&](int l) -> float * { return smem + (size_t)(l - 1) * N; };
     auto Rrow = [&](int l) -> float * { return smem + (size_t)(n + l - 2) * N; };
-    // component labels of an event; they alias L level 1, which is dead from
-    // the end of an R sweep until the next L sweep rewrites it
-    int32_t *const lab = reinterpret_cast<int32_t *>(smem);
+    // component labels of stages 1..m (m = 2..n) at an event live in L level
+    // m-1: the L levels are dead from the end of an R sweep until the next L
+    // sweep rewrites them, so the labels of every m drawn at one event are
+    // kept for its later attempts
+    auto labs = [&](int m) -> int32_t * { return reinterpret_cast<int32_t *>(Lrow(m - 1)); };
     // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
     // counts, [40 + s] stage s pairs across waves, [64..95] wave partials of
     // the decision hash (lo, hi), [100..101] the root row's stage bits,
@@ -318,6 +320,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
             // ---- partial permutation of one subgraph (Alg. 1 partialPermute) ----
             if (it == next_reset) {
                 int n_zero = 0;
+                uint32_t have = 0;  // the m whose labels this event has computed
                 for (int attempt = 0; attempt < 64; ++attempt) {
                     const int rr = 2 + (int)draw_below(st, (uint32_t)(a.P_range - 1));
                     const int x = 1 + (int)draw_below(st, (uint32_t)a.P_level);
@@ -335,25 +338,32 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     // that changes nothing leaves them equal across every pair,
                     // so each component holds its smallest row.  On an unpermuted
                     // block one sweep reaches the minimum (a butterfly), the next
-                    // confirms it.  (The previous attempt's reads of the labels
-                    // end at its barriers.)
+                    // confirms it.  The orders do not change between the attempts
+                    // of an event, so labels already computed for this m are
+                    // reused (each row reads back its own).
+                    int32_t *const lab = labs(m);
                     int lj = j;
-                    if (row) lab[j] = j;
-                    __syncthreads();
-                    for (int sweep = 0;; ++sweep) {
-                        bool c = false;
-                        for (int s = 1; s <= m; ++s) {
-                            if (s > 1) stage_sync(s);
-                            if (row) {
-                                const int w = lab[partner(j, s)];
-                                if (w < lj) {
-                                    lj = w;
-                                    lab[j] = w;
-                                    c = true;
+                    if ((have >> m) & 1u) {
+                        if (row) lj = lab[j];
+                    } else {
+                        have |= 1u << m;
+                        if (row) lab[j] = j;
+                        __syncthreads();
+                        for (int sweep = 0;; ++sweep) {
+                            bool c = false;
+                            for (int s = 1; s <= m; ++s) {
+                                if (s > 1) stage_sync(s);
+                                if (row) {
+                                    const int w = lab[partner(j, s)];
+                                    if (w < lj) {
+                                        lj = w;
+                                        lab[j] = w;
+                                        c = true;
+                                    }
                                 }
                             }
+                            if (!wg_any(c, 128 + 16 * (sweep & 1))) break;
                         }
-                        if (!wg_any(c, 128 + 16 * (sweep & 1))) break;
                     }
                     // components (their smallest rows) and the one of rank blk
                     const bool is_root = row && lj == j;
