@@ -79,8 +79,8 @@ struct Alg1Lds {
     // partner's values of those in registers, and L level n is read only by
     // its own row
     static constexpr size_t msg_floats = (size_t)(2 * n - 2) * N;
-    // + 192 control words + the rows' syndrome columns (read at every decision)
-    static constexpr size_t bytes = msg_floats * 4 + 192 * 4 + (size_t)N * 4;
+    // + 352 control words + the rows' syndrome columns (read at every decision)
+    static constexpr size_t bytes = msg_floats * 4 + 352 * 4 + (size_t)N * 4;
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
@@ -98,13 +98,14 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
     // sweep rewrites them, so the labels of every m drawn at one event are
     // kept for its later attempts
     auto labs = [&](int m) -> int32_t * { return reinterpret_cast<int32_t *>(Lrow(m - 1)); };
-    // misc: [0] frame, [1] flag, [3] root, [4..19] wave partials, [20..35] wave
-    // counts, [40 + s] stage s pairs across waves, [64..95] wave partials of
-    // the decision hash (lo, hi), [100..101] the root row's stage bits,
-    // [128..159] per-wave flags of the label passes (two sets, by pass
-    // parity), [160..175] per-wave flags of the block check
+    // misc: [0] frame, [3] root, [4..19] wave partials, [40 + s] stage s pairs
+    // across waves, [64..95] wave partials of the decision hash (lo, hi),
+    // [100..101] the root row's stage bits, [128..159] per-wave flags of the
+    // label sweeps (two sets, by sweep parity), [160..175] per-wave member
+    // counts and column flags of the block test, [192 + 16 (m-2) + w] wave w's
+    // count of component roots for stages 1..m
     int32_t *const misc = reinterpret_cast<int32_t *>(smem + Alg1Lds<NLOG>::msg_floats);
-    uint32_t *const synl = reinterpret_cast<uint32_t *>(misc + 192);
+    uint32_t *const synl = reinterpret_cast<uint32_t *>(misc + 352);
     const float alpha = a.alpha;
     const float inf = __builtin_huge_valf();
     auto Lv = [&](int l, int j) -> float & { return Lrow(l)[j]; };
@@ -130,14 +131,6 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
         v += __shfl_xor(v, 4, 16);
         v += __shfl_xor(v, 8, 16);
         return __builtin_amdgcn_readlane(v, 0);
-    };
-    // per-wave population counts of a predicate, published in misc[20 + w]
-    auto wave_counts = [&](bool v) -> uint64_t {
-        const uint64_t mask = __ballot(v);
-        __syncthreads();
-        if (lane == 0) misc[20 + wave] = __popcll(mask);
-        __syncthreads();
-        return mask;
     };
     // (called once per iteration, from the decision: the previous reads of
     // misc[4 + w] are ordered before these writes by the barrier that ends
@@ -342,8 +335,10 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     // of an event, so labels already computed for this m are
                     // reused (each row reads back its own).
                     int32_t *const lab = labs(m);
+                    int32_t *const rcnt = misc + 192 + 16 * (m - 2);
                     int lj = j;
-                    if ((have >> m) & 1u) {
+                    const bool fresh = !((have >> m) & 1u);
+                    if (!fresh) {
                         if (row) lj = lab[j];
                     } else {
                         have |= 1u << m;
@@ -365,10 +360,15 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                             if (!wg_any(c, 128 + 16 * (sweep & 1))) break;
                         }
                     }
-                    // components (their smallest rows) and the one of rank blk
+                    // components (their smallest rows) and the one of rank blk;
+                    // the per-wave root counts are published with the labels
                     const bool is_root = row && lj == j;
-                    const uint64_t rmask = wave_counts(is_root);
-                    const int cnt = lane < nwaves ? misc[20 + lane] : 0;
+                    const uint64_t rmask = __ballot(is_root);
+                    if (fresh) {
+                        if (lane == 0) rcnt[wave] = __popcll(rmask);
+                        __syncthreads();
+                    }
+                    const int cnt = lane < nwaves ? rcnt[lane] : 0;
                     const int total = sum16(cnt), before = sum16(lane < wave ? cnt : 0);
                     if (total != nblocks) continue;
                     if (is_root && before + __popcll(rmask & ((1ull << lane) - 1)) == blk) {
@@ -384,9 +384,18 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     bool mixed = false;
                     if (member)
                         for (int s = rl; s <= m; ++s) mixed |= obit(ordw, s) != obit(rord, s);
-                    wave_counts(member);
-                    const int members = sum16(lane < nwaves ? misc[20 + lane] : 0);
-                    const bool bad = wg_any(mixed, 160);
+                    // one exchange: each wave's member count and column flag
+                    // (the previous attempt read these slots before the root
+                    // barrier above)
+                    {
+                        const int mc = __popcll(__ballot(member));
+                        const bool mx = __ballot(mixed) != 0;
+                        if (lane == 0) misc[160 + wave] = mc | (mx ? 0x10000 : 0);
+                    }
+                    __syncthreads();
+                    const int mv = lane < nwaves ? misc[160 + lane] : 0;
+                    const int members = sum16(mv & 0xffff);
+                    const bool bad = __ballot((mv >> 16) != 0) != 0;
                     if (bad || members != (1 << m)) continue;
                     // a new non-identity order of the bits of stages rl..m
                     int8_t bits[kMaxLog], cand[kMaxLog];
