@@ -16,8 +16,8 @@
 // row carries its own order (4 bits per stage in registers) and every L and R
 // level that a partner reads lives in LDS, (2n-2) N floats (the channel level
 // and the prior are static per frame, so each row holds its partners' values
-// of those in registers).  At N = 1024 that is 73 KiB, and two frames share a
-// CU.
+// of those in registers).  At N = 1024 that is 72 KiB (77 KiB with the
+// control words and the syndrome columns), and two frames share a CU.
 //
 // One thread per row (up to 1024 rows).  At each stage a row computes its own
 // output of its processing element (Sec. II-B): with j' the partner of row j,
@@ -34,12 +34,13 @@
 // sweep reads, R levels) and by one barrier after the R sweep (its reads of
 // L levels, rewritten by the next L sweep or an event's labels).  At an
 // event the chosen block's first row publishes its order, which every row
-// compares with its own.  The
-// random draws come from a SplitMix64 stream per frame (seed + (frame + 1) * golden ratio, as in the
-// CPU reference decoder) that every thread advances identically, so all
-// control decisions are uniform.  The component labels of stages 1..m are
-// found by propagating the smallest row index over the pairs until nothing
-// changes; blocks are ranked by their smallest row.
+// compares with its own.  The random draws come from a SplitMix64 stream per
+// frame, started at seed + (frame + 1) * golden ratio, that every thread
+// advances identically, so all control decisions are uniform.  The component
+// labels of stages 1..m (the smallest row of each component) come from
+// stage-ordered sweeps of pairwise minima, repeated until one changes
+// nothing, and are kept for the event's later draws of the same m; blocks are
+// ranked by their smallest row.
 #include <climits>
 
 #include "bp_core.h"
@@ -84,7 +85,7 @@ struct Alg1Lds {
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
-// 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 73 KiB)
+// 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 77 KiB)
 template <int NLOG, bool SCALED>
 __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) {
     constexpr int N = 1 << NLOG, n = NLOG;
