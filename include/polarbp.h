@@ -61,8 +61,8 @@ typedef struct pc_code pc_code;
  * the min-sum scale, the first iteration at which the stop test is applied,
  * Sec. IV, and the check function of the processing element, Sec. II-B).
  * PC_CHECK_EXACT needs alpha = 1 and is built for the decode entry points
- * with the default launch shape or rho = 2 (not for Algorithm 1, the batched
- * decoder or the decision history).  It is evaluated in FP32 as
+ * with the default launch shape or rho = 2, and for Algorithm 1 (not for the
+ * batched decoder or the decision history).  It is evaluated in FP32 as
  * sgn sgn [min(|x|,|y|) + ln(1 + e^-(|x|+|y|)) - ln(1 + e^-||x|-|y||)] on the
  * hardware exp2/log2 (about 1e-7 absolute per check node), so it agrees with
  * an FP64 evaluation to rounding, not bit for bit.                          */

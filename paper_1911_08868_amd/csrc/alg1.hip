@@ -85,8 +85,17 @@ struct Alg1Lds {
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
 
+// Check function of the processing elements: CN 0 min-sum, 1 scaled min-sum
+// (both in sign-magnitude form, bit for bit the FP32 oracle's), 2 the exact
+// boxplus (FP32 on the hardware exp2/log2).
+template <int CN>
+__device__ __forceinline__ float alg1_check(float x, float y, float alpha) {
+    if constexpr (CN == 2) return cnode_exact(x, y);
+    else return cnode<CN == 1>(x, y, alpha);
+}
+
 // 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 77 KiB)
-template <int NLOG, bool SCALED>
+template <int NLOG, int CN>
 __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) {
     constexpr int N = 1 << NLOG, n = NLOG;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -255,7 +264,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const float B = s == 1 ? pch : Lrow(s - 1)[p];
                     const float C = s == n ? ppr : Rrow(s)[p];
                     // top: f(L[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + L[j]
-                    const float c = cnode<SCALED>(top ? A : C, top ? B + C : B, alpha);
+                    const float c = alg1_check<CN>(top ? A : C, top ? B + C : B, alpha);
                     Lown[s] = top ? c : c + A;
                     if (s < n) Lv(s, j) = Lown[s];
                 }
@@ -302,7 +311,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const float Q = Lrow(s - 1)[p];
                     const float S = s == n ? ppr : Rrow(s)[p];
                     // top: f(R[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + R[j]
-                    const float c = cnode<SCALED>(top ? P : S, top ? Q + S : Q, alpha);
+                    const float c = alg1_check<CN>(top ? P : S, top ? Q + S : Q, alpha);
                     Rown[s - 1] = top ? c : c + P;
                     Rv(s - 1, j) = Rown[s - 1];
                 }
@@ -457,11 +466,11 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
 }
 
 template <int NLOG>
-static int run_alg1_n(const Alg1Args &a, bool scaled, hipStream_t s) {
+static int run_alg1_n(const Alg1Args &a, int cn, hipStream_t s) {
     constexpr size_t lds = Alg1Lds<NLOG>::bytes;
     static_assert(lds <= 160 * 1024, "Algorithm 1 frame exceeds LDS");
     const int threads = Alg1Lds<NLOG>::threads;
-    auto kern = scaled ? k_alg1<NLOG, true> : k_alg1<NLOG, false>;
+    auto kern = cn == 2 ? k_alg1<NLOG, 2> : cn == 1 ? k_alg1<NLOG, 1> : k_alg1<NLOG, 0>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
@@ -512,15 +521,15 @@ int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_par
     a.seed = pp.seed;
     a.hist = d_hist;
     a.H = H;
-    const bool scaled = bp.alpha != 1.0f;
+    const int cn = bp.check == PC_CHECK_EXACT ? 2 : bp.alpha != 1.0f ? 1 : 0;
     switch (n) {
-        case 4: return run_alg1_n<4>(a, scaled, s);
-        case 5: return run_alg1_n<5>(a, scaled, s);
-        case 6: return run_alg1_n<6>(a, scaled, s);
-        case 7: return run_alg1_n<7>(a, scaled, s);
-        case 8: return run_alg1_n<8>(a, scaled, s);
-        case 9: return run_alg1_n<9>(a, scaled, s);
-        default: return run_alg1_n<10>(a, scaled, s);
+        case 4: return run_alg1_n<4>(a, cn, s);
+        case 5: return run_alg1_n<5>(a, cn, s);
+        case 6: return run_alg1_n<6>(a, cn, s);
+        case 7: return run_alg1_n<7>(a, cn, s);
+        case 8: return run_alg1_n<8>(a, cn, s);
+        case 9: return run_alg1_n<9>(a, cn, s);
+        default: return run_alg1_n<10>(a, cn, s);
     }
 }
 

@@ -317,7 +317,6 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
         if (exact || d_hist) return fail(PC_ENOTSUP, "noise injection is built for min-sum without history");
     }
     if (mode == PC_PP_ALG1) {
-        if (exact) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for min-sum");
         if (cfg && (cfg->rho || cfg->slots || cfg->grid))
             return fail(PC_EINVAL, "Algorithm 1 takes no launch shape (one frame per workgroup)");
         return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, d_hist, H,

@@ -130,6 +130,54 @@ def test_whole_decodes_agree(orc, pbp, N, K, cw, poly, snr, ppk, opk):
     assert e_gpu <= e_ms + 3 * math.sqrt(max(e_ms, 1)), (e_gpu, e_ms)
 
 
+@pytest.mark.parametrize("iters,first_reset", [(1, 0), (3, 1), (5, 2)])
+def test_algorithm1_early_messages_within_rounding(orc, pbp, iters, first_reset):
+    # Algorithm 1 with the exact boxplus: its events depend on the draws only,
+    # so both sides permute the same blocks; the u-side messages after a few
+    # iterations (events after iterations 1 and 2 included) within rounding
+    oc = orc.construct(256, 144, 2.5, 16, 0x1021)
+    F = 48
+    msg = synth.message_bits(300 + iters, F, oc.K_msg)
+    _, x = orc.encode(oc, msg)
+    llr = synth.awgn_llr(x, 1.5, oc.K_msg, seed=300 + iters)
+    bp = pbp.BPParams(max_iter=iters, stop=pbp.STOP_NONE, check=pbp.CHECK_EXACT)
+    t = dict(P_range=5, P_level=4, D=0, N_min=1, first_reset=first_reset, seed=4)
+    soft = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=pbp.PP_ALG1, **t))[3]
+    ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=iters, stop=orc.STOP_NONE, fp32=False,
+                                               exact_boxplus=True, pp_mode=orc.PP_ALG1, **t),
+                     soft=True, threads=8)
+    scale = np.maximum(np.abs(ref.soft_u), np.abs(llr).max(1, keepdims=True))
+    ratio = np.abs(soft - ref.soft_u) / scale
+    assert ratio.max() <= TOL, f"max relative deviation {ratio.max():.3e}"
+
+
+@pytest.mark.parametrize("N,K,table", [(512, 333, (9, 8, 50, 15)), (1024, 512, (2, 6, 8, 4))])
+def test_algorithm1_whole_decodes_agree(orc, pbp, N, K, table):
+    # Table I parameter sets with the exact boxplus.  The events reset parts
+    # of the graph every few iterations, which lets rounding-level differences
+    # steer slowly converging frames apart (they stop at another iteration,
+    # nearly always on the same message), so: frames the oracle decodes within
+    # 20 iterations decided alike, 95% of all it decodes, and error counts
+    # inside each other's intervals
+    F = 300
+    oc, msg, llr = _frames(orc, N, K, 24, 0x1864CFB, F, 2.25 if N == 1024 else 2.75, seed=N + 5)
+    P_range, P_level, D, N_min = table
+    t = dict(P_range=P_range, P_level=P_level, D=D, N_min=N_min, seed=6)
+    bp = pbp.BPParams(max_iter=150, stop=pbp.STOP_CRC, it_min=3, check=pbp.CHECK_EXACT)
+    m, it, ok, _ = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=pbp.PP_ALG1, **t))
+    ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=150, stop=orc.STOP_CRC, it_min=3, fp32=False,
+                                               exact_boxplus=True, pp_mode=orc.PP_ALG1, **t), threads=8)
+    same = (m == ref.msg_hat).all(1) & (it == ref.iters) & (ok == ref.ok)
+    stopped = ref.ok == 1
+    early = stopped & (ref.iters <= 20)
+    assert stopped.sum() > F // 3 and early.sum() > F // 4
+    assert same[early].mean() >= 0.99, f"only {same[early].mean():.3f} of early frames agree"
+    assert same[stopped].mean() >= 0.95, f"only {same[stopped].mean():.3f} of converged frames agree"
+    e_gpu, e_ref = int((m != msg).any(1).sum()), int((ref.msg_hat != msg).any(1).sum())
+    lo, hi = _ci(e_ref, F)
+    assert lo * F <= e_gpu <= hi * F, (e_gpu, e_ref)
+
+
 def test_large_workload_sampled(orc, pbp):
     # the 1024-bit code and last-4 schedule on 16384 frames; 40 sampled
     # frames and the slowest ones decoded by the oracle
@@ -157,9 +205,9 @@ def test_exact_rejections(pbp):
     ex = dict(max_iter=5, stop=pbp.STOP_CRC, check=pbp.CHECK_EXACT)
     with pytest.raises(pbp.PolarError):      # exact takes no scale
         pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(alpha=0.9375, **ex), pbp.PPParams())
-    with pytest.raises(pbp.PolarError):      # Algorithm 1 is min-sum only
-        pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(**ex),
-                            pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=2, D=4, N_min=2))
+    with pytest.raises(pbp.PolarError):      # no decision history with Algorithm 1 either
+        pbp.pp_mt_bp_decode_trace(code, llr, pbp.BPParams(**ex),
+                                  pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=2, D=4, N_min=2), 8)
     with pytest.raises(pbp.PolarError):      # rho 3 is built for min-sum only
         pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(**ex), pbp.PPParams(),
                             cfg=pbp.LaunchCfg(rho=3, slots=0, grid=0))
