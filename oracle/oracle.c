@@ -295,7 +295,7 @@ typedef struct {
     uint64_t seed;
     int32_t fp32;
     int32_t exact_boxplus;
-    float noise_sigma; /* > 0: noise injected at the trellis events (modes 0, 1) */
+    float noise_sigma; /* > 0: noise injected at the trellis events (modes 0, 1, 2) */
 } or_params;
 
 typedef struct {
@@ -342,7 +342,9 @@ static int check_g(const code_t *c, const double *Lu, const double *Ru, const do
  * event of the fixed schedules (after iterations T, 2T, ...; also when the
  * pool has one entry and the graph stays) the channel level is set to
  * y_j + sigma g(frame, e, j), e = it / T, with fresh noise per event and the
- * received LLR y_j.  g is an Irwin-Hall approximation of N(0,1): the sum of
+ * received LLR y_j.  Algorithm 1 does the same at each of its events (Sec. III,
+ * spaced by Eq. 2), after the partial permutation, with e = 1, 2, ... counting
+ * the frame's events (an event whose draws all fail counts too).  g is an Irwin-Hall approximation of N(0,1): the sum of
  * the twelve 16-bit fields of three SplitMix64 outputs, each field k read as
  * the uniform (k + 1/2) / 2^16, minus 6.  The generator starts from the state
  * seed ^ frame * 0x9E3779B97F4A7C15 ^ e * 0xC2B2AE3D27D4EB4F
@@ -600,6 +602,14 @@ typedef struct {
     int rc;
 } job_t;
 
+/* the channel level after the noise injection of event e */
+static void inject_noise(const or_params *p, const float *y, int64_t f, int32_t e, int32_t N, double *L) {
+    for (int32_t j = 0; j < N; j++) {
+        double g = (double)or_noise_gauss(p->seed, f, e, j);
+        L[j] = rnd(p->fp32, (double)y[j] + rnd(p->fp32, (double)p->noise_sigma * g));
+    }
+}
+
 static void decode_frames(job_t *jb) {
     const code_t *c = jb->c;
     const or_params *p = jb->p;
@@ -629,6 +639,7 @@ static void decode_frames(job_t *jb) {
         uint64_t st = p->seed + (uint64_t)(f + 1) * 0x9E3779B97F4A7C15ull;
         int32_t next_reset = (p->pp_mode == 2) ? alg1_first_reset(N, n, p) : 0;
         int32_t it_done = p->max_iter;
+        int32_t events = 0;
         int okv = 0;
         for (int32_t it = 1; it <= p->max_iter; it++) {
             one_iteration(&ar, N, &sc, L, R);
@@ -652,21 +663,16 @@ static void decode_frames(job_t *jb) {
                     if (kk >= 2) zero_levels(N, L, R, n - kk + 1, n - 1, 0, N);
                     cur_q = q;
                 }
-                if (p->noise_sigma > 0.0f) {
-                    /* fresh channel noise on the received LLRs */
-                    int32_t e = it / p->T;
-                    for (int32_t j = 0; j < N; j++) {
-                        double g = (double)or_noise_gauss(p->seed, f, e, j);
-                        L[j] = rnd(p->fp32, (double)jb->llr[f * N + j] +
-                                                rnd(p->fp32, (double)p->noise_sigma * g));
-                    }
-                }
+                /* fresh channel noise on the received LLRs */
+                if (p->noise_sigma > 0.0f) inject_noise(p, jb->llr + f * N, f, it / p->T, N, L);
             } else if (p->pp_mode == 2 && it == next_reset) {
                 int32_t nz = 0;
                 alg1_event(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, rows, mark);
                 int32_t add = p->D > 0 ? nz / p->D : 0;
                 if (add < p->N_min) add = p->N_min;
                 next_reset = it + add;
+                events++;
+                if (p->noise_sigma > 0.0f) inject_noise(p, jb->llr + f * N, f, events, N, L);
             }
         }
         if (p->stop == 0 || !okv) {
@@ -721,7 +727,8 @@ static int decode_impl(int32_t N, int32_t K, const int32_t *info_idx, int32_t cr
                             p->P_level > n - 1 || p->N_min < 1))
         return OR_EINVAL;
     if (p->exact_boxplus && p->fp32) return OR_EINVAL;
-    if (!(p->noise_sigma >= 0.0f) || (p->noise_sigma > 0.0f && p->pp_mode != 0 && p->pp_mode != 1))
+    if (!(p->noise_sigma >= 0.0f) || (p->noise_sigma > 0.0f && p->pp_mode != 0 && p->pp_mode != 1 &&
+                                      p->pp_mode != 2))
         return OR_EINVAL;
     if (F == 0) return OR_OK;
     code_t c = {N, n, K, crc_width, crc_poly, info_idx, NULL};

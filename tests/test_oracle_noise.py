@@ -1,8 +1,9 @@
 """Pins for the oracle's noise injection at the trellis events (the
 future-work combination of Sec. V with the noise-aided BP of Table I): the
 Gaussian draw against SplitMix64's published outputs and the Irwin-Hall
-moments, and the event step rebuilt from plain BP iterations, the noisy
-channel level and the permuted graph."""
+moments, the event step of the fixed schedules rebuilt from plain BP
+iterations, the noisy channel level and the permuted graph, and Algorithm
+1's channel level after a known number of events."""
 import json
 import os
 
@@ -81,10 +82,37 @@ def test_zero_sigma_is_the_plain_schedule(orc):
     assert not np.array_equal(a.soft_u, c.soft_u)
 
 
-def test_noise_is_rejected_outside_the_fixed_schedules(orc):
+@pytest.mark.parametrize("T0,d,E", [(3, 50, 1), (2, 4, 3)])
+def test_algorithm1_channel_level_after_events(orc, T0, d, E):
+    # Algorithm 1 with events after iterations T0, T0 + d, ... (D = 0 spaces
+    # them by N_min = d): the channel level left at the end is y + sigma g of
+    # the last event, e = E counting the frame's events, in single precision
+    code, msg, llr = _frames(orc, 128, 80, 8, 0x07, 4, 1.5, 13)
+    seed, sigma = 21, np.float32(0.6)
+    max_iter = T0 + (E - 1) * d + 1
+    p = orc.DecodeParams(max_iter=max_iter, stop=orc.STOP_NONE, pp_mode=orc.PP_ALG1, P_range=4,
+                         P_level=3, D=0, N_min=d, first_reset=T0, seed=seed, noise_sigma=float(sigma))
+    r = orc.decode(code, llr, p, state=True)
+    for f in range(4):
+        g = np.array([orc.noise_gauss(seed, f, E, j) for j in range(128)], np.float32)
+        want = (llr[f] + (sigma * g).astype(np.float32)).astype(np.float32)
+        np.testing.assert_array_equal(r.state[f, 0][0], want)
+
+
+def test_algorithm1_noise_only_at_events(orc):
+    # no event within the budget: the noise changes nothing; with events it does
+    code, msg, llr = _frames(orc, 128, 80, 8, 0x07, 20, 1.5, 17)
+    kw = dict(max_iter=30, stop=orc.STOP_CRC, pp_mode=orc.PP_ALG1, P_range=4, P_level=3, D=4, N_min=3,
+              seed=5)
+    a = orc.decode(code, llr, orc.DecodeParams(first_reset=40, **kw), soft=True)
+    b = orc.decode(code, llr, orc.DecodeParams(first_reset=40, noise_sigma=0.6, **kw), soft=True)
+    assert np.array_equal(a.soft_u, b.soft_u) and np.array_equal(a.iters, b.iters)
+    c = orc.decode(code, llr, orc.DecodeParams(noise_sigma=0.6, **kw), soft=True)
+    e = orc.decode(code, llr, orc.DecodeParams(**kw), soft=True)
+    assert not np.array_equal(c.soft_u, e.soft_u)
+
+
+def test_noise_is_rejected_without_events(orc):
     code, msg, llr = _frames(orc, 64, 40, 8, 0x07, 2, 2.0, 1)
     with pytest.raises(ValueError):
         orc.decode(code, llr, orc.DecodeParams(max_iter=5, noise_sigma=0.5))
-    with pytest.raises(ValueError):
-        orc.decode(code, llr, orc.DecodeParams(max_iter=5, pp_mode=orc.PP_ALG1, P_range=2,
-                                               P_level=2, D=2, N_min=2, noise_sigma=0.5))
