@@ -91,18 +91,20 @@ typedef struct {
     uint64_t seed;
     float noise_sigma; /* 0, or noise injected at the events (below)        */
 } pc_pp_params;
-/* Noise injection (PC_PP_LASTK / PC_PP_FULL with noise_sigma > 0; the paper
- * names noise injection together with partial permutations as future work,
- * Sec. V, beside the noise-aided BP of Table I, sigma^2 = 0.36).  At every
- * event, after iteration T, 2T, ... (also when pool_Q = 1 and the graph
- * stays), the channel level becomes y_j + noise_sigma * g with y_j the
- * received LLR and g an Irwin-Hall approximation of N(0,1): the twelve
- * 16-bit fields k of three SplitMix64 outputs from the state
+/* Noise injection (PC_PP_LASTK / PC_PP_FULL / PC_PP_ALG1 with noise_sigma >
+ * 0; the paper names noise injection together with partial permutations as
+ * future work, Sec. V, beside the noise-aided BP of Table I, sigma^2 = 0.36).
+ * At every event, after iteration T, 2T, ... of the fixed schedules (also
+ * when pool_Q = 1 and the graph stays) or after each event of Algorithm 1,
+ * the channel level becomes y_j + noise_sigma * g with y_j the received LLR
+ * and g an Irwin-Hall approximation of N(0,1): the twelve 16-bit fields k of
+ * three SplitMix64 outputs from the state
  * seed ^ frame*0x9E3779B97F4A7C15 ^ e*0xC2B2AE3D27D4EB4F ^ j*0x165667B19E3779F9
- * (e = iteration / T, j = row), each read as (k + 1/2)/2^16, summed, minus 6;
- * the product and the sum round once each in single precision.  Built with
- * min-sum and the default launch shape or rho = 2; not with Algorithm 1, the
- * batched decoder, the decision history or weighted BP.                    */
+ * (j = row; e = iteration / T, or for Algorithm 1 the count 1, 2, ... of the
+ * frame's events), each read as (k + 1/2)/2^16, summed, minus 6; the product
+ * and the sum round once each in single precision.  Built with min-sum and
+ * the default launch shape or rho = 2; not with the batched decoder, the
+ * decision history or weighted BP.                                         */
 /* PC_PP_ALG1 (Algorithm 1, Sec. III and Table I).  At an event a frame draws
  * rho_range ~ U{2..P_range}, rho_level = min(U{1..P_level}, n - rho_range + 1)
  * and one of the N/2^m connected blocks of stages 1..m of its current graph

@@ -64,6 +64,8 @@ struct Alg1Args {
     uint64_t seed;
     uint64_t *hist;  // [F][H] decision hashes, or NULL
     int32_t H;
+    float noise_sigma;  // > 0: channel level y + sigma g(frame, e, j) after event e
+    uint64_t noise_seed;
 };
 
 // uniform integer in [0, m): the high 32 bits of the next output, scaled by m
@@ -187,14 +189,21 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
     sfor<0, kPk>([&](auto i) { pk[i] = 0u; });
     auto cpart = [&](int s) -> int { return (int)((pk[(s - 1) / 3] >> (10 * ((s - 1) % 3))) & 1023u); };
     float pch = 0.f, ppr = 0.f;
-    auto load_pairs = [&](bool row, int j, const float *src) {
+    // the channel level of row r after event e (e = 0: none yet): the received
+    // LLR plus the event's noise, each product and sum rounded once
+    auto channel = [&](const float *src, int64_t frame, int e, int r) -> float {
+        if (e == 0) return src[r];
+        const float z = a.noise_sigma * noise_gauss(a.noise_seed, frame, e, r);
+        return src[r] + z;
+    };
+    auto load_pairs = [&](bool row, int j, const float *src, int64_t frame, int e) {
         sfor<0, kPk>([&](auto i) { pk[i] = 0u; });
         sfor<1, n + 1>([&](auto s) {
             const uint32_t p = row ? (uint32_t)partner(j, s) : 0u;
             pk[(s - 1) / 3] |= p << (10 * ((s - 1) % 3));
         });
         if (row) {
-            pch = src[partner(j, 1)];
+            pch = channel(src, frame, e, partner(j, 1));
             ppr = a.meta[partner(j, n)] == -2 ? inf : 0.f;
         }
     };
@@ -246,8 +255,9 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
             const int v = full > a.N_min ? full : a.N_min;
             next_reset = v < a.max_iter / 2 ? v : a.max_iter / 2;
         }
+        int ev = 0;  // events so far with noise injected (Sec. V reading)
         update_cross(row);
-        load_pairs(row, j, src);
+        load_pairs(row, j, src, frame, ev);
         const uint64_t hkey = a.hist ? decision_key(j) : 0ull;
 
         int it_done = a.max_iter;
@@ -445,8 +455,13 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                 int add = a.D > 0 ? n_zero / a.D : 0;
                 if (add < a.N_min) add = a.N_min;
                 next_reset = it + add;
+                if (a.noise_sigma > 0.f) {
+                    // fresh channel noise on the received LLRs, every event
+                    ++ev;
+                    if (row) Lown[0] = channel(src, frame, ev, j);
+                }
                 update_cross(row);
-                load_pairs(row, j, src);
+                load_pairs(row, j, src, frame, ev);
             }
         }
 
@@ -521,6 +536,8 @@ int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_par
     a.seed = pp.seed;
     a.hist = d_hist;
     a.H = H;
+    a.noise_sigma = pp.noise_sigma;
+    a.noise_seed = pp.seed;
     const int cn = bp.check == PC_CHECK_EXACT ? 2 : bp.alpha != 1.0f ? 1 : 0;
     switch (n) {
         case 4: return run_alg1_n<4>(a, cn, s);

@@ -394,20 +394,24 @@ def exact_boxplus(torch, pbp, F=262144, snrs=(1.5, 2.0, 2.5, 3.0, 3.5)):
 
 def noise_aided(torch, pbp, F=65536, sigma=0.6):
     """Noise injected at the trellis events (sigma^2 = 0.36, the noise-aided BP
-    setting of Table I) with and without the last-4 permutations, beside the
-    last-4 schedule and plain BP, on N=1024 codes of rate 1/2 and 0.65 with
-    CRC-24 (K includes the CRC), at most 200 iterations, CRC stop from
-    iteration 3; events every 10 iterations."""
+    setting of Table I) with and without the last-4 permutations, and at
+    Algorithm 1's events (Table I 200-iteration set), beside the same
+    schedules without noise and plain BP, on N=1024 codes of rate 1/2 and
+    0.65 with CRC-24 (K includes the CRC), at most 200 iterations, CRC stop
+    from iteration 3; fixed-schedule events every 10 iterations."""
     import synth
     out = []
     for rate, K, snrs in (("1/2", 512, (2.0, 3.0, 3.5)), ("0.65", 666, (2.5, 3.5, 4.0))):
         code = pbp.Code(1024, K, 24, 0x1864CFB, 2.5)
         bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
         lastk = dict(mode=pbp.PP_LASTK, k=4, period_T=10, seed=1)
+        alg1 = dict(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)
         scheds = (("bp", pbp.PPParams()),
                   ("lastk4", pbp.PPParams(pool_Q=8, **lastk)),
                   ("lastk4_noise", pbp.PPParams(pool_Q=8, noise_sigma=sigma, **lastk)),
-                  ("noise_only", pbp.PPParams(pool_Q=1, noise_sigma=sigma, **lastk)))
+                  ("noise_only", pbp.PPParams(pool_Q=1, noise_sigma=sigma, **lastk)),
+                  ("alg1", pbp.PPParams(**alg1)),
+                  ("alg1_noise", pbp.PPParams(noise_sigma=sigma, **alg1)))
         for snr in snrs:
             gen = torch.Generator(device="cuda")
             gen.manual_seed(int(snr * 100) + K)
@@ -430,7 +434,8 @@ def noise_aided(torch, pbp, F=65536, sigma=0.6):
                 f"{n} fer {row[n]['fer']:.4g}" for n, _ in scheds))
     return {"workload": f"noise injected at the events (sigma^2 = {sigma * sigma:.2f}), N=1024, CRC-24, "
                         f"R = 1/2 (K=512) and 0.65 (K=666), {F} frames per point, max 200 iterations, "
-                        f"CRC stop from iteration 3, events every 10 iterations", "points": out}
+                        f"CRC stop from iteration 3, fixed-schedule events every 10 iterations, "
+                        f"Algorithm 1 with the Table I 200-iteration set", "points": out}
 
 
 def batched_mixed(torch, pbp, F=4_000_000):

@@ -2,9 +2,9 @@
 combination of Sec. V; noise-aided BP of Table I) against the FP32 oracle:
 decided bits, iteration counts, verdicts and the u-side L messages
 bit-exact (values equal, bits equal where nonzero), on the last-k and
-full-permutation schedules, noise without permutation, the G test and
-scaled min-sum; the 1024-bit workload on sampled frames; and the argument
-checks."""
+full-permutation schedules, noise without permutation, Algorithm 1, the G
+test and scaled min-sum; the 1024-bit workload on sampled frames; and the
+argument checks."""
 import numpy as np
 import pytest
 
@@ -61,6 +61,16 @@ CASES = [
      dict(mode=0, k=3, period_T=4, pool_Q=1, seed=2), dict(pp_mode=0, k=3, T=4, Q=1, seed=2), 0.6),
     (512, 256, 16, 0x1021, 160, 1.75, dict(max_iter=70, stop=2, alpha=0.9375),
      dict(mode=0, k=5, period_T=6, pool_Q=8, seed=4), dict(pp_mode=0, k=5, T=6, Q=8, seed=4), 0.45),
+    # Algorithm 1: noise after each of its events (Table I parameter sets)
+    (1024, 512, 24, 0x1864CFB, 64, 1.75, dict(max_iter=120, stop=2, it_min=3),
+     dict(mode=2, P_range=2, P_level=6, D=8, N_min=4, seed=6),
+     dict(pp_mode=2, P_range=2, P_level=6, D=8, N_min=4, seed=6), 0.6),
+    (512, 333, 24, 0x1864CFB, 96, 2.5, dict(max_iter=150, stop=2, it_min=3),
+     dict(mode=2, P_range=9, P_level=8, D=50, N_min=15, seed=7),
+     dict(pp_mode=2, P_range=9, P_level=8, D=50, N_min=15, seed=7), 0.6),
+    (64, 40, 8, 0x07, 300, 1.5, dict(max_iter=60, stop=2, alpha=0.9375),
+     dict(mode=2, P_range=4, P_level=3, D=2, N_min=2, seed=8),
+     dict(pp_mode=2, P_range=4, P_level=3, D=2, N_min=2, seed=8), 0.3),
 ]
 
 
@@ -108,9 +118,10 @@ def test_noise_rejections(pbp):
             pbp.pp_mt_bp_decode(code, llr, bp, pbp.PPParams(noise_sigma=bad, **lastk))
     with pytest.raises(pbp.PolarError):          # no events without a fixed schedule
         pbp.pp_mt_bp_decode(code, llr, bp, pbp.PPParams(noise_sigma=0.6))
-    with pytest.raises(pbp.PolarError):
-        pbp.pp_mt_bp_decode(code, llr, bp, pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=2, D=4,
-                                                        N_min=2, noise_sigma=0.6))
+    with pytest.raises(pbp.PolarError):          # Algorithm 1 with noise: min-sum only
+        pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(max_iter=5, check=pbp.CHECK_EXACT),
+                            pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=2, D=4, N_min=2,
+                                         noise_sigma=0.6))
     with pytest.raises(pbp.PolarError):          # exact boxplus: min-sum only
         pbp.pp_mt_bp_decode(code, llr, pbp.BPParams(max_iter=5, check=pbp.CHECK_EXACT),
                             pbp.PPParams(noise_sigma=0.6, **lastk))
