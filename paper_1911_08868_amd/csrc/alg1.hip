@@ -24,8 +24,8 @@
 // the top row needs f(L_{s-1}[j], L_{s-1}[j'] + R_s[j']) and the bottom row
 // f(R_s[j'], L_{s-1}[j']) + L_{s-1}[j] (L sweep), so both read the same three
 // values and select operands without branching; the R sweep is alike.  The
-// bottom output alone adds a term, which keeps the sign of a zero exactly as
-// the per-pair form gives it.  Consecutive stages need a workgroup barrier
+// check function is the clamp form of min-sum with an L operand as the bound,
+// as in the fixed-schedule kernels.  Consecutive stages need a workgroup barrier
 // only if some row of the reading stage pairs on a bit >= 6, i.e. with a row
 // of another wave; a per-stage flag, recomputed after every event, says so,
 // and the other stages are ordered by the wave's own in-order LDS accesses
@@ -88,12 +88,13 @@ struct Alg1Lds {
 };
 
 // Check function of the processing elements: CN 0 min-sum, 1 scaled min-sum
-// (both in sign-magnitude form, bit for bit the FP32 oracle's), 2 the exact
-// boxplus (FP32 on the hardware exp2/log2).
+// (the clamp form: equal to the FP32 oracle's values, a zero possibly with
+// the other sign; x is the bound, an L operand as in the fixed-schedule
+// kernels), 2 the exact boxplus (FP32 on the hardware exp2/log2).
 template <int CN>
 __device__ __forceinline__ float alg1_check(float x, float y, float alpha) {
     if constexpr (CN == 2) return cnode_exact(x, y);
-    else return cnode<CN == 1>(x, y, alpha);
+    else return cnode_clamp<CN>(x, y, alpha);
 }
 
 // 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 77 KiB)
@@ -273,8 +274,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const float A = Lown[s - 1];
                     const float B = s == 1 ? pch : Lrow(s - 1)[p];
                     const float C = s == n ? ppr : Rrow(s)[p];
-                    // top: f(L[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + L[j]
-                    const float c = alg1_check<CN>(top ? A : C, top ? B + C : B, alpha);
+                    // top: f(L[j], L[j'] + R[j']); bottom: f(L[j'], R[j']) + L[j]
+                    const float c = alg1_check<CN>(top ? A : B, top ? B + C : C, alpha);
                     Lown[s] = top ? c : c + A;
                     if (s < n) Lv(s, j) = Lown[s];
                 }
@@ -320,8 +321,8 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
                     const float P = Rown[s];
                     const float Q = Lrow(s - 1)[p];
                     const float S = s == n ? ppr : Rrow(s)[p];
-                    // top: f(R[j], L[j'] + R[j']); bottom: f(R[j'], L[j']) + R[j]
-                    const float c = alg1_check<CN>(top ? P : S, top ? Q + S : Q, alpha);
+                    // top: f(L[j'] + R[j'], R[j]); bottom: f(L[j'], R[j']) + R[j]
+                    const float c = alg1_check<CN>(top ? Q + S : Q, top ? P : S, alpha);
                     Rown[s - 1] = top ? c : c + P;
                     Rv(s - 1, j) = Rown[s - 1];
                 }

@@ -1,7 +1,8 @@
 """GPU parity of Algorithm 1 (random-subgraph partial permutations, Eq. 2
 reset spacing) against the oracle: decided bits, iteration counts, verdicts
-and the u-side L messages (bit-exact; this kernel keeps the sign-magnitude
-check function) on the paper's Table I parameter sets and edge settings."""
+bit-exact and the u-side L messages equal as FP32 values and bit-identical
+wherever nonzero (the clamp form of min-sum may give a zero the other sign)
+on the paper's Table I parameter sets and edge settings."""
 import json
 import os
 
@@ -49,7 +50,9 @@ def _assert_parity(got, ref, tag):
     bad = np.nonzero((m != ref.msg_hat).any(1) | (it != ref.iters) | (ok != ref.ok))[0]
     assert bad.size == 0, f"{tag}: {bad.size} frames differ, first {bad[:5]} iters {it[bad[:5]]} vs {ref.iters[bad[:5]]}"
     want = ref.soft_u.astype(np.float32)
-    assert np.array_equal(soft.view(np.uint32), want.view(np.uint32)), f"{tag}: soft messages differ"
+    assert np.array_equal(soft, want), f"{tag}: soft messages differ"
+    nz = soft != 0
+    assert np.array_equal(soft.view(np.uint32)[nz], want.view(np.uint32)[nz]), f"{tag}: soft bits differ"
 
 
 @pytest.mark.parametrize("cw,poly", [(16, 0x1021), (24, 0x1864CFB)])
