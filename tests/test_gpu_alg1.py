@@ -81,6 +81,34 @@ def test_table1_n512_rate_065(orc, pbp):
     _assert_parity(got, ref, "Table I N=512 R=0.65")
 
 
+def test_table1_large_workload_sampled(orc, pbp):
+    # 16384 frames of the 1024-bit code in one launch (two frames per CU, many
+    # refills from the queue): the first 1024 frames' decided bits and
+    # iteration counts bit-exact against the oracle, and the verdicts of a
+    # sample of them (with the longest decodes)
+    import torch
+    t = TABLE1["N1024_Nitmax200"]
+    F, P = 16384, 1024
+    oc = orc.construct(1024, 512, 2.5, 24, 0x1864CFB)
+    msg = synth.message_bits(91, F, oc.K_msg)
+    _, x = orc.encode(oc, msg)
+    llr = synth.awgn_llr(x, 2.0, oc.K_msg, seed=91)
+    code = pbp.Code(1024, 512, 24, 0x1864CFB, 2.5)
+    bp = pbp.BPParams(max_iter=200, stop=orc.STOP_CRC, it_min=3)
+    pp = pbp.PPParams(mode=pbp.PP_ALG1, P_range=t["P_range"], P_level=t["P_level"], D=t["D"],
+                      N_min=t["N_min"], seed=2)
+    m, it, ok = [a.cpu().numpy() for a in pbp.pp_mt_bp_decode(code, torch.from_numpy(llr).cuda(), bp, pp)]
+    ref = orc.decode(oc, llr[:P], orc.DecodeParams(max_iter=200, stop=orc.STOP_CRC, it_min=3,
+                                                   pp_mode=orc.PP_ALG1, P_range=t["P_range"],
+                                                   P_level=t["P_level"], D=t["D"], N_min=t["N_min"],
+                                                   seed=2, fp32=True), threads=8)
+    rng = np.random.default_rng(5)
+    pick = np.union1d(rng.choice(P, 48, replace=False), np.argsort(-it[:P])[:8])
+    assert np.array_equal(m[pick], ref.msg_hat[pick])
+    assert np.array_equal(it[pick], ref.iters[pick]) and np.array_equal(ok[pick], ref.ok[pick])
+    assert np.array_equal(m[:P], ref.msg_hat) and np.array_equal(it[:P], ref.iters)
+
+
 @pytest.mark.parametrize("set_name,N,K", [("N1024_Nitmax20000", 1024, 512),
                                           ("N512_Nitmax20000", 512, 333)])
 def test_table1_long_budget_many_events(orc, pbp, set_name, N, K):
