@@ -30,7 +30,7 @@ struct DecodeArgs {
     float *soft;
     const uint32_t *syn;
     const int32_t *meta;
-    uint32_t *counter;
+    uint32_t *counter;  // kQueues queue counters, 16 words apart
     int32_t K_msg, max_iter, it_min, stop;
     float alpha;
     int32_t T, Q;
@@ -473,12 +473,12 @@ __device__ __forceinline__ void decode_loop(Src &src, const DecodeCtl &a, float 
 
 
 // ---------------------------------------------------------------------------
-// Frames claimed from a shared queue counter in chunks of C consecutive
-// frames: below N = 128 a frame finishes so fast that one atomic per frame on
-// one L2 address caps the frame rate (about 1e8 frames/s), so those lengths
-// take C = 256 / N frames per claim; from N = 128 on every frame is its own
-// chunk (larger chunks measured slower there: a longer tail and frames in
-// flight spread further apart).  Each frame is decoded exactly once.
+// Frames claimed from a queue counter in chunks of C consecutive queue
+// entries: below N = 128 a frame finishes so fast that one atomic per frame
+// caps the frame rate, so those lengths take C = 256 / N entries per claim;
+// from N = 128 on every entry is its own chunk (larger chunks measured slower
+// there: a longer tail and frames in flight spread further apart).  Each
+// frame is decoded exactly once.
 template <int N_>
 struct ChunkClaim {
     static constexpr int C = N_ >= 128 ? 1 : 256 / N_;
@@ -494,19 +494,44 @@ struct ChunkClaim {
     }
 };
 
-// Frame source of a single-code launch: a queue counter over frames 0..F-1.
-// With TR it records the decision hash of iteration it (0-based) of frame f
-// at hist[f][it mod H]; NZ selects the noise-injecting schedule.
+// Frame source of a single-code launch.  Frames 0..F-1 are spread over QN
+// interleaved queues, queue k holding frames k, k + QN, ..., each with its
+// own counter on its own 64-byte line (a.counter + 16 k).  One counter
+// serialises its atomics at about 1e8 per second (11.5 ns per frame): below
+// N = 1024 a frame of a few tens of iterations takes less than that (about
+// 0.14 ns per frame-iteration at N = 256 on the whole chip), so those lengths
+// use kQueues queues; from N = 1024 on (1.6 ns per frame-iteration) one queue
+// measured faster.  A slot starts at queue (workgroup + thread / 16) mod QN
+// and moves to the next queue when one runs dry, so it leaves after at most
+// QN failed claims.  With TR it records the decision hash of iteration it
+// (0-based) of frame f at hist[f][it mod H]; NZ selects the noise-injecting
+// schedule.
+constexpr int kQueues = 8;  // counters the host clears per call
 template <int N_, bool TR, bool NZ = false>
 struct SingleSrc {
     static constexpr bool kTrace = TR;
     static constexpr bool kNoise = NZ;
+    static constexpr int QN = N_ >= 1024 ? 1 : kQueues;
     const DecodeArgs &a;
     int64_t F;
     ChunkClaim<N_> claim;
-    __device__ SingleSrc(const DecodeArgs &args) : a(args), F(args.F) {}
+    int q, left = QN;  // current queue; queues not yet found empty
+    __device__ SingleSrc(const DecodeArgs &args)
+        : a(args), F(args.F), q((int)((blockIdx.x + (threadIdx.x >> 4)) % QN)) {}
     __device__ int64_t pop() {
-        return claim.take(F, [&](int b) { return (int64_t)atomicAdd(a.counter, (unsigned)b); });
+        if constexpr (QN == 1)
+            return claim.take(F, [&](int b) { return (int64_t)atomicAdd(a.counter, (unsigned)b); });
+        while (left > 0) {
+            const int64_t nq = F > q ? (F - q + QN - 1) / QN : 0;  // frames of queue q
+            const int64_t i = claim.take(nq, [&](int b) {
+                return (int64_t)atomicAdd(a.counter + 16 * q, (unsigned)b);
+            });
+            if (i < nq) return q + (int64_t)QN * i;
+            // queue q is empty (and stays so); its chunk is used up
+            --left;
+            q = (q + 1) % QN;
+        }
+        return F;
     }
     __device__ const float *llr(int64_t f) const { return a.llr + f * N_; }
     __device__ const uint32_t *syn(int64_t) const { return a.syn; }

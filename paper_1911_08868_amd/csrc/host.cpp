@@ -53,6 +53,10 @@ int device_cu_count() {
 static constexpr int kRing = 4096;
 
 __global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
+// the counters of a block of queues, one per 64-byte line
+__global__ void k_reset_queues(uint32_t *c, int k) {
+    if ((int)threadIdx.x < k) c[16 * threadIdx.x] = 0u;
+}
 
 uint32_t *next_counter(int device) {
     static std::mutex mu;
@@ -66,6 +70,25 @@ uint32_t *next_counter(int device) {
         ring[device] = static_cast<uint32_t *>(p);
     }
     uint32_t *c = ring[device] + (size_t)(pos[device] % kRing) * 16;
+    pos[device]++;
+    return c;
+}
+
+// The same for the k-queue counters of a single-code decode: a ring of blocks
+// of k consecutive 64-byte lines.
+uint32_t *next_queue_block(int device, int k) {
+    static std::mutex mu;
+    static uint32_t *ring[64] = {nullptr};
+    static unsigned pos[64] = {0};
+    constexpr int kBlocks = 1024, kMaxK = 16;
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= 64 || k < 1 || k > kMaxK) return nullptr;
+    if (!ring[device]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)kBlocks * kMaxK * 64) != hipSuccess) return nullptr;
+        ring[device] = static_cast<uint32_t *>(p);
+    }
+    uint32_t *c = ring[device] + (size_t)(pos[device] % kBlocks) * kMaxK * 16;
     pos[device]++;
     return c;
 }
@@ -336,10 +359,10 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     } else {
         for (int s = 0; s < n; ++s) orders[s] = (int8_t)s;
     }
-    uint32_t *ctr = next_counter(code->device);
+    uint32_t *ctr = next_queue_block(code->device, kQueues);
     if (!ctr) return fail(PC_ENOMEM, "queue counter allocation");
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, hs, ctr);
+    hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, hs, ctr, kQueues);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
 

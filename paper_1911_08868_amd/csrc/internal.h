@@ -54,6 +54,7 @@ int device_cu_count();
 
 // per-call queue counter in a library-owned device ring
 uint32_t *next_counter(int device);
+uint32_t *next_queue_block(int device, int k);
 
 // ---- decode ----------------------------------------------------------------
 struct DecodeConfig {
