@@ -120,7 +120,8 @@ typedef struct {
  * of the previous event (0 if skipped; D = 0 gives N_min).  Needs
  * 2 <= P_range <= n, 1 <= P_level <= n-1, N_min >= 1.  On the GPU: N = 16 ..
  * 1024, codes with a CRC and PC_STOP_CRC or PC_STOP_NONE; one frame per
- * workgroup with every message in LDS, so no launch configuration.         */
+ * workgroup, one row per thread (messages in registers, the levels partners
+ * read in LDS), so no launch configuration.                                */
 
 /* Launch configuration picked by the autotuner; NULL selects the library's
  * table.  rho: log2 rows held per thread per level (2 or 3); slots: frames
