@@ -139,6 +139,24 @@ def test_small_workgroups_cycle_the_pool(orc, pbp, N, K, k, rho, slots):
     assert int(ref.iters.max()) > 16  # some frame went through all eight trellises
 
 
+@pytest.mark.parametrize("N,K,F", [(256, 144, 1), (256, 144, 3), (512, 256, 7), (512, 256, 9),
+                                   (128, 64, 8), (64, 40, 13), (32, 20, 5), (256, 144, 4099)])
+def test_queue_counts(orc, pbp, N, K, F):
+    # below N = 1024 the frames come from 8 interleaved queues: fewer frames
+    # than queues, counts that are no multiple of 8, chunked claims (N < 128)
+    # and a long ragged batch; every frame decoded once and exactly
+    cw, poly = (8, 0x07) if N <= 64 else (16, 0x1021)
+    oc, msg, llr = frames(orc, N, K, cw, poly, F, 2.0, seed=N + F)
+    got, ref = run_both(orc, pbp, oc, llr, 60, orc.STOP_CRC, it_min=2, pp_mode=0, k=3, T=5, Q=4,
+                        seed=3)
+    assert_parity(got, ref, f"N={N} F={F}")
+    # the decode is the frame's own: the same frames in another order decode alike
+    perm = np.random.default_rng(F).permutation(F)
+    got2, _ = run_both(orc, pbp, oc, np.ascontiguousarray(llr[perm]), 60, orc.STOP_CRC, it_min=2,
+                       pp_mode=0, k=3, T=5, Q=4, seed=3)
+    assert np.array_equal(got2[0], got[0][perm]) and np.array_equal(got2[1], got[1][perm])
+
+
 @pytest.mark.parametrize("N,K,k", [(128, 43, 4), (256, 128, 4), (512, 384, 4), (128, 96, 4),
                                    (256, 64, 3)])
 def test_mixed_lengths_parity(orc, pbp, N, K, k):
