@@ -74,7 +74,8 @@ def lib() -> ctypes.CDLL:
         L.or_classify.restype = ctypes.c_int
         L.or_wbp_forward.argtypes = [c_i32, c_i32, vp, vp, c_i64, vp, c_i32, vp, vp]
         L.or_wbp_forward.restype = ctypes.c_int
-        L.or_wbp_backward.argtypes = [c_i32, c_i32, vp, vp, c_i64, vp, c_i32, vp, vp, vp, vp]
+        L.or_wbp_backward.argtypes = [c_i32, c_i32, vp, vp, c_i64, vp, c_i32, vp, vp, vp, vp,
+                                      vp]
         L.or_wbp_backward.restype = ctypes.c_int
         L.or_bp_run.argtypes = [c_i32, c_i32, vp, vp, vp, c_d, c_i32, c_i32, vp, vp]
         L.or_bp_run.restype = ctypes.c_int
@@ -83,7 +84,7 @@ def lib() -> ctypes.CDLL:
         L.or_graph_encode.argtypes = [c_i32, vp, vp, vp]
         L.or_graph_encode.restype = ctypes.c_int
         L.or_alg1_trace.argtypes = [c_i32, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, vp, vp, vp,
-                                    vp]
+                                    vp, vp]
         L.or_alg1_trace.restype = ctypes.c_int
         L.or_sizeof_params.restype = c_i32
         L.or_sizeof_wbp_params.restype = c_i32
@@ -350,8 +351,11 @@ def wbp_forward(code: Code, llr: np.ndarray, w: np.ndarray, params: WbpParams) -
 
 
 def wbp_backward(code: Code, llr: np.ndarray, w: np.ndarray, params: WbpParams,
-                 grad_out: np.ndarray, want_llr_grad: bool = False):
-    """Reverse mode of ``wbp_forward``: returns (grad_w [T,n,2,N], grad_llr or None)."""
+                 grad_out: np.ndarray, want_llr_grad: bool = False, want_abs: bool = False):
+    """Reverse mode of ``wbp_forward``: returns (grad_w [T,n,2,N], grad_llr or
+    None), and with want_abs a third array: per weight entry, the sum over
+    every path of the reverse computation of the magnitude of the path's
+    product of derivatives (the scale of an FP32 adjoint's rounding error)."""
     llr = np.ascontiguousarray(llr, np.float32)
     w = np.ascontiguousarray(w, np.float64)
     g = np.ascontiguousarray(grad_out, np.float64)
@@ -359,13 +363,15 @@ def wbp_backward(code: Code, llr: np.ndarray, w: np.ndarray, params: WbpParams,
     F = llr.shape[0]
     gw = np.zeros_like(w)
     gl = np.zeros((F, code.N), np.float64) if want_llr_grad else None
+    ga = np.zeros_like(w) if want_abs else None
     p = params._c()
     rc = lib().or_wbp_backward(code.N, code.K, _ptr(code.info_idx), _ptr(llr), F, _ptr(w), T,
                                ctypes.byref(p), _ptr(g), _ptr(gw),
-                               _ptr(gl) if gl is not None else None)
+                               _ptr(gl) if gl is not None else None,
+                               _ptr(ga) if ga is not None else None)
     if rc:
         raise ValueError(f"or_wbp_backward rc={rc}")
-    return gw, gl
+    return (gw, gl, ga) if want_abs else (gw, gl)
 
 
 def bp_run(llr: np.ndarray, frozen: np.ndarray, n_iter: int, order=None, alpha: float = 1.0,
@@ -406,18 +412,22 @@ def graph_encode(order: np.ndarray, u) -> np.ndarray:
 
 
 def alg1_trace(N: int, P_range: int, P_level: int, D: int, N_min: int, seed: int,
-               n_events: int):
-    """Schedules and counters after each of n_events Algorithm-1 events."""
+               n_events: int, want_draws: bool = False):
+    """Schedules and counters after each of n_events Algorithm-1 events; with
+    want_draws also the accepted draw of each event, int32 [n_events, 4 + n]:
+    rho_range, x, m, block, then the new bits of stages rho_level..m
+    (rho_range = 0 for a skipped event)."""
     n = N.bit_length() - 1
     ords = np.zeros((n_events, N, n), np.int8)
     nz = np.zeros(n_events, np.int32)
     add = np.zeros(n_events, np.int32)
     zc = np.zeros(n_events, np.int32)
+    dr = np.zeros((n_events, 4 + n), np.int32)
     rc = lib().or_alg1_trace(N, P_range, P_level, D, N_min, seed, n_events, _ptr(ords),
-                             _ptr(nz), _ptr(add), _ptr(zc))
+                             _ptr(nz), _ptr(add), _ptr(zc), _ptr(dr))
     if rc:
         raise ValueError(f"or_alg1_trace rc={rc}")
-    return ords, nz, add, zc
+    return (ords, nz, add, zc, dr) if want_draws else (ords, nz, add, zc)
 
 
 def bp_continue(L: np.ndarray, R: np.ndarray, n_iter: int, order=None, alpha: float = 1.0,

@@ -519,9 +519,11 @@ static int32_t label_components(const sched_t *sc, int32_t N, int m, int32_t *la
     return nl;
 }
 
+/* draw (or NULL) receives the accepted draw: rho_range, x, m, the block and
+ * the new bits of stages rho_level..m, for the pins of the draw distributions */
 static int alg1_event(const sched_t *sc, int32_t N, double *L, double *R, uint64_t *st,
                       int32_t P_range, int32_t P_level, int32_t *n_zero, int32_t *label,
-                      int32_t *queue) {
+                      int32_t *queue, int32_t *draw) {
     int n = sc->n;
     for (int attempt = 0; attempt < 64; attempt++) {
         int rr = 2 + (int)draw_below(st, (uint32_t)(P_range - 1));
@@ -566,9 +568,17 @@ static int alg1_event(const sched_t *sc, int32_t N, double *L, double *R, uint64
             }
         }
         *n_zero = (1 << m) * (rr - 1);
+        if (draw) {
+            draw[0] = rr;
+            draw[1] = x;
+            draw[2] = m;
+            draw[3] = blk;
+            for (int i = 0; i < rr; i++) draw[4 + i] = cand[i];
+        }
         return 1;
     }
     *n_zero = 0;
+    if (draw) draw[0] = 0;
     return 0;
 }
 
@@ -667,7 +677,7 @@ static void decode_frames(job_t *jb) {
                 if (p->noise_sigma > 0.0f) inject_noise(p, jb->llr + f * N, f, it / p->T, N, L);
             } else if (p->pp_mode == 2 && it == next_reset) {
                 int32_t nz = 0;
-                alg1_event(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, rows, mark);
+                alg1_event(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, rows, mark, NULL);
                 int32_t add = p->D > 0 ? nz / p->D : 0;
                 if (add < p->N_min) add = p->N_min;
                 next_reset = it + add;
@@ -990,12 +1000,124 @@ int or_wbp_forward(int32_t N, int32_t K, const int32_t *info_idx, const float *l
     return OR_OK;
 }
 
+/* Reverse mode of one frame.  gout: d loss / d o of the frame's rows;
+ * adds into grad_w [T][n][2][N]; grad_llr (or NULL): the frame's adjoint of
+ * the channel LLRs.  The forward state Ls, Rs, Rsweep must hold the frame's
+ * forward pass.
+ *
+ * absolute = 1 runs the same pass with every local derivative and every
+ * upstream adjoint replaced by its magnitude: the min-sum routing is
+ * unchanged, sgn() becomes 1, weights and forward messages enter as |w| and
+ * |g|.  Each entry then holds the sum, over every path of the reverse
+ * computation, of the magnitudes of the path's product of derivatives.  A
+ * reverse pass that rounds each product and each sum once (with at most k
+ * roundings on any path from the output to an entry) lies within
+ * k u / (1 - k u) times that sum of the exact value, u the unit roundoff:
+ * the bound the GPU adjoint is checked against.                            */
+static double mg(int absolute, double v) { return absolute ? fabs(v) : v; }
+static double sg(int absolute, double v) { return absolute ? 1.0 : sgnb(v); }
+
+static void wbp_backward_frame(const wctx_t *w, const double *wt, const double *gout,
+                               int absolute, const double *Ls, const double *Rs,
+                               const double *Rw, double *gL, double *gR, double *gRs,
+                               double *gRin, double *grad_w, double *grad_llr) {
+    const int32_t N = w->N, n = w->n, T = w->T;
+    const or_wbp_params *p = w->p;
+    const size_t lvl = (size_t)(n + 1) * N;
+    for (size_t i = 0; i < lvl; i++) gRs[i] = 0.0;
+    for (int32_t t = T - 1; t >= 0; t--) {
+        const double *L = Ls + (size_t)t * lvl;
+        const double *Rin_state = Rs + (size_t)t * lvl;
+        const double *Rsw = Rw + (size_t)t * lvl;
+        const int8_t *ord = w->pool + (size_t)wbp_order_at(w, t) * n;
+        const int kperm = (p->pp_mode == 0) ? p->k : 0;
+        /* an event after iteration t reset the inner levels: nothing of
+         * iteration t reaches iteration t+1 through them                 */
+        if (t + 1 < T && p->pp_mode == 0 && w->pool_q > 1 &&
+            wbp_order_at(w, t + 1) != wbp_order_at(w, t)) {
+            for (int lev = n - p->k + 1; lev <= n - 1; lev++)
+                for (int32_t j = 0; j < N; j++) gRs[(size_t)lev * N + j] = 0.0;
+        }
+        for (size_t i = 0; i < lvl; i++) { gL[i] = 0.0; gR[i] = 0.0; gRin[i] = 0.0; }
+        /* R sweep outputs at levels 1..n-1 feed iteration t+1 */
+        for (int lev = 1; lev <= n - 1; lev++)
+            for (int32_t j = 0; j < N; j++) gR[(size_t)lev * N + j] = gRs[(size_t)lev * N + j];
+        if (t == T - 1)
+            for (int32_t j = 0; j < N; j++) gL[(size_t)n * N + j] = mg(absolute, gout[j]);
+        /* reverse of the R sweep: stages 1..n */
+        for (int s = 1; s <= n; s++) {
+            int b = ord[s - 1];
+            const double *wr = wt + (((size_t)t * n + (s - 1)) * 2 + 1) * N;
+            double *gwr = grad_w + (((size_t)t * n + (s - 1)) * 2 + 1) * N;
+            for (int32_t j = 0; j < N; j++) {
+                if ((j >> b) & 1) continue;
+                int32_t jp = j | (1 << b);
+                double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
+                double r1 = Rsw[(size_t)s * N + j], r2 = Rsw[(size_t)s * N + jp];
+                double a = rnd(p->fp32, l2 + r2);
+                double g1 = ms0(r1, a), g2 = ms0(r1, l1);
+                double go1 = gR[(size_t)(s - 1) * N + j], go2 = gR[(size_t)(s - 1) * N + jp];
+                const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
+                gwr[pj] += go1 * mg(absolute, g1);
+                gwr[pjp] += go2 * mg(absolute, g2);
+                double d1 = go1 * mg(absolute, wr[pj]), d2 = go2 * mg(absolute, wr[pjp]);
+                double ga = 0.0;
+                if (fabs(r1) <= fabs(a)) gR[(size_t)s * N + j] += d1 * sg(absolute, a);
+                else ga += d1 * sg(absolute, r1);
+                gL[(size_t)(s - 1) * N + jp] += ga;
+                gR[(size_t)s * N + jp] += ga;
+                if (fabs(r1) <= fabs(l1)) gR[(size_t)s * N + j] += d2 * sg(absolute, l1);
+                else gL[(size_t)(s - 1) * N + j] += d2 * sg(absolute, r1);
+                gR[(size_t)s * N + jp] += go2;
+            }
+        }
+        /* reverse of the L sweep: stages n..1 */
+        for (int s = n; s >= 1; s--) {
+            int b = ord[s - 1];
+            const double *wl = wt + (((size_t)t * n + (s - 1)) * 2 + 0) * N;
+            double *gwl = grad_w + (((size_t)t * n + (s - 1)) * 2 + 0) * N;
+            for (int32_t j = 0; j < N; j++) {
+                if ((j >> b) & 1) continue;
+                int32_t jp = j | (1 << b);
+                double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
+                double r1 = Rin_state[(size_t)s * N + j], r2 = Rin_state[(size_t)s * N + jp];
+                double a = rnd(p->fp32, l2 + r2);
+                double f1 = ms0(l1, a), f2 = ms0(r1, l1);
+                double go1 = gL[(size_t)s * N + j], go2 = gL[(size_t)s * N + jp];
+                const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
+                gwl[pj] += go1 * mg(absolute, f1);
+                gwl[pjp] += go2 * mg(absolute, f2);
+                double d1 = go1 * mg(absolute, wl[pj]), d2 = go2 * mg(absolute, wl[pjp]);
+                double ga = 0.0;
+                if (fabs(l1) <= fabs(a)) gL[(size_t)(s - 1) * N + j] += d1 * sg(absolute, a);
+                else ga += d1 * sg(absolute, l1);
+                gL[(size_t)(s - 1) * N + jp] += ga;
+                gRin[(size_t)s * N + jp] += ga;
+                if (fabs(r1) <= fabs(l1)) gRin[(size_t)s * N + j] += d2 * sg(absolute, l1);
+                else gL[(size_t)(s - 1) * N + j] += d2 * sg(absolute, r1);
+                gL[(size_t)(s - 1) * N + jp] += go2;
+            }
+        }
+        /* adjoint of the R state entering iteration t (levels 1..n-1) */
+        for (size_t i = 0; i < lvl; i++) gRs[i] = 0.0;
+        for (int lev = 1; lev <= n - 1; lev++)
+            for (int32_t j = 0; j < N; j++) gRs[(size_t)lev * N + j] = gRin[(size_t)lev * N + j];
+        if (grad_llr) {
+            if (t == T - 1)
+                for (int32_t j = 0; j < N; j++) grad_llr[j] = 0.0;
+            for (int32_t j = 0; j < N; j++) grad_llr[j] += gL[j];
+        }
+    }
+}
+
 /* reverse mode: grad_out [F][N] = d loss / d o; accumulates grad_w
  * [T][n][2][N] (summed over frames, in frame order, in double) and writes
- * grad_llr [F][N] if non-NULL.                                              */
+ * grad_llr [F][N] if non-NULL.  grad_w_abs (or NULL) receives the same sums
+ * taken over magnitudes (absolute = 1 above), the per-entry scale of the
+ * rounding error of an FP32 adjoint.                                        */
 int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *llr, int64_t F,
                     const double *wt, int32_t T, const or_wbp_params *p, const double *grad_out,
-                    double *grad_w, double *grad_llr) {
+                    double *grad_w, double *grad_llr, double *grad_w_abs) {
     int n = ilog2_exact(N);
     if (n < 0 || T < 1 || !p || !wt || !grad_out || !grad_w || !info_idx || K < 1 || K > N)
         return OR_EINVAL;
@@ -1021,93 +1143,16 @@ int or_wbp_backward(int32_t N, int32_t K, const int32_t *info_idx, const float *
     if (p->pp_mode == 0) pq = or_trellis_pool(n, p->k, p->Q, p->seed, pool);
     else for (int s = 0; s < n; s++) pool[s] = (int8_t)s;
     wctx_t w = {N, n, T, pool, pq, p, frozen};
-    memset(grad_w, 0, sizeof(double) * (size_t)T * n * 2 * N);
+    const size_t nw = (size_t)T * n * 2 * N;
+    memset(grad_w, 0, sizeof(double) * nw);
+    if (grad_w_abs) memset(grad_w_abs, 0, sizeof(double) * nw);
     for (int64_t f = 0; f < F; f++) {
         wbp_forward_frame(&w, llr + f * N, wt, Ls, Rs, Rw);
-        for (size_t i = 0; i < lvl; i++) gRs[i] = 0.0;
-        for (int32_t t = T - 1; t >= 0; t--) {
-            const double *L = Ls + (size_t)t * lvl;
-            const double *Rin_state = Rs + (size_t)t * lvl;
-            const double *Rsw = Rw + (size_t)t * lvl;
-            const int8_t *ord = pool + (size_t)wbp_order_at(&w, t) * n;
-            const int kperm = (p->pp_mode == 0) ? p->k : 0;
-            /* an event after iteration t reset the inner levels: nothing of
-             * iteration t reaches iteration t+1 through them                 */
-            if (t + 1 < T && p->pp_mode == 0 && pq > 1 &&
-                wbp_order_at(&w, t + 1) != wbp_order_at(&w, t)) {
-                for (int lev = n - p->k + 1; lev <= n - 1; lev++)
-                    for (int32_t j = 0; j < N; j++) gRs[(size_t)lev * N + j] = 0.0;
-            }
-            for (size_t i = 0; i < lvl; i++) { gL[i] = 0.0; gR[i] = 0.0; gRin[i] = 0.0; }
-            /* R sweep outputs at levels 1..n-1 feed iteration t+1 */
-            for (int lev = 1; lev <= n - 1; lev++)
-                for (int32_t j = 0; j < N; j++) gR[(size_t)lev * N + j] = gRs[(size_t)lev * N + j];
-            if (t == T - 1)
-                for (int32_t j = 0; j < N; j++) gL[(size_t)n * N + j] = grad_out[f * N + j];
-            /* reverse of the R sweep: stages 1..n */
-            for (int s = 1; s <= n; s++) {
-                int b = ord[s - 1];
-                const double *wr = wt + (((size_t)t * n + (s - 1)) * 2 + 1) * N;
-                double *gwr = grad_w + (((size_t)t * n + (s - 1)) * 2 + 1) * N;
-                for (int32_t j = 0; j < N; j++) {
-                    if ((j >> b) & 1) continue;
-                    int32_t jp = j | (1 << b);
-                    double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
-                    double r1 = Rsw[(size_t)s * N + j], r2 = Rsw[(size_t)s * N + jp];
-                    double a = rnd(p->fp32, l2 + r2);
-                    double g1 = ms0(r1, a), g2 = ms0(r1, l1);
-                    double go1 = gR[(size_t)(s - 1) * N + j], go2 = gR[(size_t)(s - 1) * N + jp];
-                    const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
-                    gwr[pj] += go1 * g1;
-                    gwr[pjp] += go2 * g2;
-                    double d1 = go1 * wr[pj], d2 = go2 * wr[pjp];
-                    double ga = 0.0;
-                    if (fabs(r1) <= fabs(a)) gR[(size_t)s * N + j] += d1 * sgnb(a);
-                    else ga += d1 * sgnb(r1);
-                    gL[(size_t)(s - 1) * N + jp] += ga;
-                    gR[(size_t)s * N + jp] += ga;
-                    if (fabs(r1) <= fabs(l1)) gR[(size_t)s * N + j] += d2 * sgnb(l1);
-                    else gL[(size_t)(s - 1) * N + j] += d2 * sgnb(r1);
-                    gR[(size_t)s * N + jp] += go2;
-                }
-            }
-            /* reverse of the L sweep: stages n..1 */
-            for (int s = n; s >= 1; s--) {
-                int b = ord[s - 1];
-                const double *wl = wt + (((size_t)t * n + (s - 1)) * 2 + 0) * N;
-                double *gwl = grad_w + (((size_t)t * n + (s - 1)) * 2 + 0) * N;
-                for (int32_t j = 0; j < N; j++) {
-                    if ((j >> b) & 1) continue;
-                    int32_t jp = j | (1 << b);
-                    double l1 = L[(size_t)(s - 1) * N + j], l2 = L[(size_t)(s - 1) * N + jp];
-                    double r1 = Rin_state[(size_t)s * N + j], r2 = Rin_state[(size_t)s * N + jp];
-                    double a = rnd(p->fp32, l2 + r2);
-                    double f1 = ms0(l1, a), f2 = ms0(r1, l1);
-                    double go1 = gL[(size_t)s * N + j], go2 = gL[(size_t)s * N + jp];
-                    const int32_t pj = weight_pos(j, ord, n, s, kperm), pjp = weight_pos(jp, ord, n, s, kperm);
-                    gwl[pj] += go1 * f1;
-                    gwl[pjp] += go2 * f2;
-                    double d1 = go1 * wl[pj], d2 = go2 * wl[pjp];
-                    double ga = 0.0;
-                    if (fabs(l1) <= fabs(a)) gL[(size_t)(s - 1) * N + j] += d1 * sgnb(a);
-                    else ga += d1 * sgnb(l1);
-                    gL[(size_t)(s - 1) * N + jp] += ga;
-                    gRin[(size_t)s * N + jp] += ga;
-                    if (fabs(r1) <= fabs(l1)) gRin[(size_t)s * N + j] += d2 * sgnb(l1);
-                    else gL[(size_t)(s - 1) * N + j] += d2 * sgnb(r1);
-                    gL[(size_t)(s - 1) * N + jp] += go2;
-                }
-            }
-            /* adjoint of the R state entering iteration t (levels 1..n-1) */
-            for (size_t i = 0; i < lvl; i++) gRs[i] = 0.0;
-            for (int lev = 1; lev <= n - 1; lev++)
-                for (int32_t j = 0; j < N; j++) gRs[(size_t)lev * N + j] = gRin[(size_t)lev * N + j];
-            if (grad_llr) {
-                if (t == T - 1)
-                    for (int32_t j = 0; j < N; j++) grad_llr[f * N + j] = 0.0;
-                for (int32_t j = 0; j < N; j++) grad_llr[f * N + j] += gL[j];
-            }
-        }
+        wbp_backward_frame(&w, wt, grad_out + f * N, 0, Ls, Rs, Rw, gL, gR, gRs, gRin, grad_w,
+                           grad_llr ? grad_llr + f * N : NULL);
+        if (grad_w_abs)
+            wbp_backward_frame(&w, wt, grad_out + f * N, 1, Ls, Rs, Rw, gL, gR, gRs, gRin,
+                               grad_w_abs, NULL);
     }
     free(frozen); free(pool); free(Ls); free(Rs); free(Rw);
     free(gL); free(gR); free(gRs); free(gRin);
@@ -1179,10 +1224,11 @@ int or_graph_encode(int32_t N, const int8_t *ord, const uint8_t *u, uint8_t *x) 
 /* Apply n_events Algorithm-1 events to the original graph of length N.
  * ord_out: [n_events][N][n] schedule after each event; nzero_out,
  * reset_add_out: [n_events] N_zero and the Eq. 2 increment; zeroed_out:
- * [n_events] number of (level, row) nodes reset, counted on the state.      */
+ * [n_events] number of (level, row) nodes reset, counted on the state;
+ * draw_out (or NULL): [n_events][4 + n] the accepted draw of each event.     */
 int or_alg1_trace(int32_t N, int32_t P_range, int32_t P_level, int32_t D, int32_t N_min,
                   uint64_t seed, int32_t n_events, int8_t *ord_out, int32_t *nzero_out,
-                  int32_t *reset_add_out, int32_t *zeroed_out) {
+                  int32_t *reset_add_out, int32_t *zeroed_out, int32_t *draw_out) {
     int n = ilog2_exact(N);
     if (n < 0 || P_range < 2 || P_range > n || P_level < 1 || P_level > n - 1 || D < 1)
         return OR_EINVAL;
@@ -1200,7 +1246,8 @@ int or_alg1_trace(int32_t N, int32_t P_range, int32_t P_level, int32_t D, int32_
     for (int32_t e = 0; e < n_events; e++) {
         for (size_t t = 0; t < lvl; t++) { L[t] = 1.0; R[t] = 1.0; }
         int32_t nz = 0;
-        alg1_event(&sc, N, L, R, &st, P_range, P_level, &nz, lab, q);
+        alg1_event(&sc, N, L, R, &st, P_range, P_level, &nz, lab, q,
+                   draw_out ? draw_out + (size_t)e * (4 + n) : NULL);
         int32_t add = nz / D;
         if (add < N_min) add = N_min;
         int32_t z = 0;

@@ -71,17 +71,52 @@ def test_gradient_central_differences(orc, T, pp):
     assert np.all(gw[T - 1, :, 1] == 0.0)
 
 
-def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
-    """Independent unrolled weighted min-sum BP in torch (float64), rows vectorised."""
+def _ms(x, y):
+    sx = torch.where(torch.signbit(x), -1.0, 1.0)
+    sy = torch.where(torch.signbit(y), -1.0, 1.0)
+    return torch.where(x.abs() <= y.abs(), sy * x, sx * y)
+
+
+class _AbsMul(torch.autograd.Function):
+    """w * x whose backward uses the magnitudes of the local derivatives."""
+
+    @staticmethod
+    def forward(ctx, w, x):
+        ctx.save_for_backward(w, x)
+        return w * x
+
+    @staticmethod
+    def backward(ctx, g):
+        w, x = ctx.saved_tensors
+        return g.abs() * x.abs(), g.abs() * w.abs()
+
+
+class _AbsMs(torch.autograd.Function):
+    """Min-sum whose backward routes the magnitude of the adjoint to the
+    smaller input (ties to the first), as the derivative's magnitude is 1."""
+
+    @staticmethod
+    def forward(ctx, x, y):
+        ctx.save_for_backward(x, y)
+        return _ms(x, y)
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y = ctx.saved_tensors
+        first = x.abs() <= y.abs()
+        return torch.where(first, g.abs(), 0.0), torch.where(first, 0.0, g.abs())
+
+
+def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev, absolute=False):
+    """Independent unrolled weighted min-sum BP in torch (float64), rows
+    vectorised.  absolute=True: the same forward values, with a backward
+    whose every local derivative is replaced by its magnitude."""
     F, N = llr.shape
     T, n = w.shape[0], w.shape[1]
     prior = torch.where(torch.as_tensor(frozen.astype(bool)), torch.tensor(S_PRIOR, dtype=torch.float64),
                         torch.tensor(0.0, dtype=torch.float64))
-
-    def ms(x, y):
-        sx = torch.where(torch.signbit(x), -1.0, 1.0)
-        sy = torch.where(torch.signbit(y), -1.0, 1.0)
-        return torch.where(x.abs() <= y.abs(), sy * x, sx * y)
+    ms = _AbsMs.apply if absolute else _ms
+    mul = _AbsMul.apply if absolute else torch.mul
 
     R = [torch.zeros(F, N, dtype=torch.float64) for _ in range(n + 1)]
     R[n] = prior.expand(F, N)
@@ -109,9 +144,9 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
             r1, r2 = R[s][:, top], R[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
             out = out.index_put((torch.arange(F)[:, None], top[None, :]),
-                                w[t, s - 1, 0, pos[top]] * ms(l1, l2 + r2))
+                                mul(w[t, s - 1, 0, pos[top]], ms(l1, l2 + r2)))
             out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
-                                w[t, s - 1, 0, pos[bot]] * ms(r1, l1) + l2)
+                                mul(w[t, s - 1, 0, pos[bot]], ms(r1, l1)) + l2)
             L[s] = out
         if t == T - 1:
             return L[n] + R[n]
@@ -126,9 +161,9 @@ def _torch_wbp(llr, frozen, w, pool_orders, k, T_ev):
             r1, r2 = newR[s][:, top], newR[s][:, bot]
             out = torch.zeros(F, N, dtype=torch.float64)
             out = out.index_put((torch.arange(F)[:, None], top[None, :]),
-                                w[t, s - 1, 1, pos[top]] * ms(r1, l2 + r2))
+                                mul(w[t, s - 1, 1, pos[top]], ms(r1, l2 + r2)))
             out = out.index_put((torch.arange(F)[:, None], bot[None, :]),
-                                w[t, s - 1, 1, pos[bot]] * ms(r1, l1) + r2)
+                                mul(w[t, s - 1, 1, pos[bot]], ms(r1, l1)) + r2)
             newR[s - 1] = out
         R = newR
 
@@ -155,3 +190,31 @@ def test_gradient_matches_torch_autograd(orc, N, T, pp):
     (out * torch.as_tensor(g)).sum().backward()
     gw, _ = orc.wbp_backward(code, llr, w, p, g)
     np.testing.assert_allclose(gw, wt.grad.numpy(), rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("N,T,pp", [(16, 3, False), (32, 4, True), (64, 3, False)])
+def test_gradient_magnitude_sums_match_torch(orc, N, T, pp):
+    # the oracle's magnitude pass (the per-entry error scale of an FP32
+    # adjoint) against torch autograd of the independent implementation with
+    # every local derivative replaced by its magnitude; weights of both signs
+    n = N.bit_length() - 1
+    code, llr = _setup(orc, N, N // 2, 3, 40 + N)
+    rng = np.random.default_rng(N + 1)
+    w = rng.uniform(0.6, 1.4, (T, n, 2, N)) * rng.choice([-1.0, 1.0], (T, n, 2, N))
+    g = rng.normal(size=(3, N))
+    g[:, code.frozen.astype(bool)] = 0.0
+    if pp:
+        p = orc.WbpParams(pp_mode=orc.PP_LASTK, k=3, T_ev=2, Q=3, seed=9)
+        pool, k, tev = orc.trellis_pool(n, 3, 3, seed=9), 3, 2
+    else:
+        p, pool, k, tev = orc.WbpParams(), None, 0, 1
+    wt = torch.tensor(w, dtype=torch.float64, requires_grad=True)
+    out = _torch_wbp(llr, code.frozen, wt, pool, k, tev, absolute=True)
+    out.backward(torch.as_tensor(np.abs(g)))
+    gw, _, ga = orc.wbp_backward(code, llr, w, p, g, want_abs=True)
+    np.testing.assert_allclose(ga, wt.grad.numpy(), rtol=1e-10, atol=1e-10)
+    # a sum of path magnitudes bounds the signed sum of the same paths, and
+    # the gradient itself is unchanged by the extra pass
+    assert np.all(np.abs(gw) <= ga * (1 + 1e-12))
+    assert np.array_equal(gw, orc.wbp_backward(code, llr, w, p, g)[0])
+    assert np.count_nonzero(ga) > 0.1 * ga.size
