@@ -161,6 +161,14 @@ int polar_trellis_pool(int32_t n, int32_t k, int32_t Q, uint64_t seed, int8_t *o
 int polar_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
                  void *stream);
 
+/* The information bits u_A of each frame (Sec. II-A: the message bits, then
+ * their CRC, most significant first, on the information set in ascending row
+ * order; Sec. IV: CRC-aided codes): d_msg uint8 [F][K - crc_width] (0/1),
+ * d_u_info uint8 [F][K].  These are the targets of a loss on the decoder's
+ * output LLRs at the information rows.                                      */
+int polar_info_bits(const pc_code *code, const uint8_t *d_msg, uint8_t *d_u_info, int64_t F,
+                    void *stream);
+
 /* Standard min-sum BP decoding (Sec. II-B) of F frames.
  * d_llr float [F][N] channel LLRs (4-byte aligned, finite for defined
  * results); d_msg_hat uint8 [F][K - crc_width] decided message bits;
@@ -172,9 +180,12 @@ int bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_pa
 
 /* Partially permuted multi-trellis BP (Algorithm 1 with the fixed schedules
  * of pc_pp_params).  Arguments as bp_decode.  The decode entry points enqueue
- * kernels only (the queue counter is reset by a kernel, no memset): after one
- * warm-up call on the device, a call can be captured into a HIP graph and
- * replayed with new data in the same buffers.                              */
+ * kernels only (the queue counters are reset by a kernel, no memset): after
+ * one eager call on the device (which allocates the library's counters), a
+ * call can be captured into a HIP graph and replayed with new data in the
+ * same buffers.  A captured call keeps its own counters for good (at most
+ * 1024 captured calls per device), so replays may overlap eager calls and
+ * other graphs on other streams.                                           */
 int pp_mt_bp_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_bp_params *bp,
                     const pc_pp_params *pp, uint8_t *d_msg_hat, int32_t *d_iters, uint8_t *d_ok,
                     void *stream);

@@ -13,7 +13,7 @@ from ._lib import (PolarError, PC_OK, PC_EINVAL, PC_ENOTSUP, PC_EHIP, PC_ENOMEM,
                    STOP_NONE, STOP_G, STOP_CRC, PP_NONE, PP_LASTK, PP_FULL, PP_ALG1,
                    ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED,
                    CHECK_MINSUM, CHECK_EXACT, lib, library_path)
-from .api import (Code, BPParams, PPParams, LaunchCfg, trellis_pool, encode, bp_decode,
+from .api import (Code, BPParams, PPParams, LaunchCfg, trellis_pool, encode, info_bits, bp_decode,
                   pp_mt_bp_decode, pp_mt_bp_decode_trace, classify_errors, decode_batched,
                   batched_workspace_bytes, wbp_workspace_bytes, wbp_forward, wbp_backward)
 
@@ -21,7 +21,7 @@ __all__ = [
     "PolarError", "PC_OK", "PC_EINVAL", "PC_ENOTSUP", "PC_EHIP", "PC_ENOMEM",
     "STOP_NONE", "STOP_G", "STOP_CRC", "PP_NONE", "PP_LASTK", "PP_FULL", "PP_ALG1",
     "lib", "library_path", "Code", "BPParams", "PPParams", "LaunchCfg", "trellis_pool",
-    "encode", "bp_decode", "pp_mt_bp_decode", "decode_batched", "batched_workspace_bytes",
+    "encode", "info_bits", "bp_decode", "pp_mt_bp_decode", "decode_batched", "batched_workspace_bytes",
     "wbp_workspace_bytes", "wbp_forward", "wbp_backward", "pp_mt_bp_decode_trace",
     "classify_errors", "CHECK_MINSUM", "CHECK_EXACT", "ERR_CORRECT", "ERR_FALSE_CONVERGED", "ERR_OSCILLATION", "ERR_UNCONVERGED",
 ]

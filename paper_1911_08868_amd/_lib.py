@@ -17,7 +17,7 @@ EXPORTS = [
     "polar_encode", "bp_decode", "pp_mt_bp_decode", "pp_mt_bp_decode_ex",
     "polar_batched_workspace_bytes", "pp_mt_bp_decode_batched", "wbp_workspace_bytes",
     "wbp_forward", "wbp_backward", "polar_strerror", "polar_last_error",
-    "pp_mt_bp_decode_trace", "polar_classify_errors",
+    "pp_mt_bp_decode_trace", "polar_classify_errors", "polar_info_bits",
 ]
 CHECK_MINSUM, CHECK_EXACT = 0, 1
 ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED = 0, 1, 2, 3
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "polar_code_query": ([vp, vp, vp], ctypes.c_int),
         "polar_trellis_pool": ([i32, i32, i32, u64, vp], ctypes.c_int),
         "polar_encode": ([vp, vp, vp, i64, vp], ctypes.c_int),
+        "polar_info_bits": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "bp_decode": ([vp, vp, i64, P(BPParamsC), vp, vp, vp, vp], ctypes.c_int),
         "pp_mt_bp_decode": ([vp, vp, i64, P(BPParamsC), P(PPParamsC), vp, vp, vp, vp],
                             ctypes.c_int),

@@ -137,6 +137,20 @@ def encode(code: Code, msg, out=None):
     return out
 
 
+def info_bits(code: Code, msg, out=None):
+    """msg uint8 [F, K_msg] on the device -> u on the information rows,
+    uint8 [F, K] (the message, then its CRC), ``polar_info_bits``."""
+    torch = _torch()
+    F = msg.shape[0]
+    _need(msg, torch.uint8, (F, code.K_msg), "msg")
+    if out is None:
+        out = torch.empty((F, code.K), dtype=torch.uint8, device=msg.device)
+    _need(out, torch.uint8, (F, code.K), "out")
+    check(lib().polar_info_bits(code.handle, _ptr(msg), _ptr(out), F, _stream(msg.device)),
+          "polar_info_bits")
+    return out
+
+
 def _decode(code, llr, bp, pp, soft, cfg, out):
     torch = _torch()
     F = llr.shape[0]

@@ -51,9 +51,18 @@ def _units():
     return units
 
 
-def _compile(unit, extra):
+def _headers_mtime():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs.append(os.path.join(os.path.dirname(HERE), "include", "polarbp.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(unit, extra, incremental=False, hdr_mtime=0.0):
     src, obj, defs = unit
     out = os.path.join(BUILD, obj)
+    if incremental and os.path.exists(out) and \
+            os.path.getmtime(out) > max(os.path.getmtime(src), hdr_mtime):
+        return out
     cmd = [HIPCC, *FLAGS, *extra, *defs, "-c", src, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -61,13 +70,17 @@ def _compile(unit, extra):
     return out
 
 
-def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool = False,
+          incremental: bool = False) -> str:
+    """Compile every unit and link.  incremental=True (development only)
+    skips a unit whose object is newer than its source and every header."""
     os.makedirs(BUILD, exist_ok=True)
     extra = extra or []
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = _units()
+    hm = _headers_mtime()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda u: _compile(u, extra), units))
+        objs = list(ex.map(lambda u: _compile(u, extra, incremental, hm), units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -80,5 +93,5 @@ def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

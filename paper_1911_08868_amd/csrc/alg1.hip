@@ -498,8 +498,6 @@ static int run_alg1_n(const Alg1Args &a, int cn, hipStream_t s) {
     return e == hipSuccess ? PC_OK : hip_fail(e, "Algorithm 1 launch");
 }
 
-__global__ void k_alg1_reset_counter(uint32_t *c) { *c = 0u; }
-
 int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_params &bp,
                 const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
                 uint64_t *d_hist, int32_t H, hipStream_t s) {
@@ -509,9 +507,9 @@ int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_par
         return fail(PC_ENOTSUP, "Algorithm 1 on the GPU checks with the CRC (a code with a CRC, stop none or CRC)");
     if (pp.P_range < 2 || pp.P_range > n || pp.P_level < 1 || pp.P_level > n - 1 || pp.N_min < 1 || pp.D < 0)
         return fail(PC_EINVAL, "Algorithm 1 needs 2 <= P_range <= n, 1 <= P_level <= n-1, N_min >= 1, D >= 0");
-    uint32_t *ctr = next_counter(c->device);
-    if (!ctr) return fail(PC_ENOMEM, "queue counter allocation");
-    hipLaunchKernelGGL(k_alg1_reset_counter, dim3(1), dim3(1), 0, s, ctr);
+    uint32_t *ctr = counter_block(c->device, s);
+    if (!ctr) return PC_ENOMEM;
+    hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, s, ctr, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
     Alg1Args a{};

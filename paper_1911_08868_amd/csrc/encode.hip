@@ -5,7 +5,9 @@
 // of each set message bit) to the last crc_width information rows, and the
 // n XOR butterflies v[j] ^= v[j + 2^b] (rows j with bit b = 0) run in LDS,
 // one barrier per stage; pairs of a stage are disjoint, so each stage is a
-// single parallel step.
+// single parallel step.  With ua != NULL the kernel also writes u on the
+// information rows, in ascending row order (the message, then its CRC); with
+// x == NULL it stops there.
 #include <algorithm>
 
 #include "bp_core.h"
@@ -14,7 +16,7 @@
 namespace pbp {
 
 __global__ void __launch_bounds__(256)
-k_encode(const uint8_t *msg, uint8_t *x, int64_t F, int N, int n, int K, int kmsg, int cw,
+k_encode(const uint8_t *msg, uint8_t *x, uint8_t *ua, int64_t F, int N, int n, int K, int kmsg, int cw,
          const int32_t *info, const uint32_t *crc_bit) {
     extern __shared__ uint8_t u[];
     __shared__ uint32_t red[4];
@@ -39,6 +41,14 @@ k_encode(const uint8_t *msg, uint8_t *x, int64_t F, int N, int n, int K, int kms
             for (int t = tid; t < cw; t += blockDim.x)
                 u[info[kmsg + t]] = (uint8_t)((crc >> (cw - 1 - t)) & 1u);
         }
+        if (ua) {
+            __syncthreads();
+            for (int i = tid; i < K; i += blockDim.x) ua[f * K + i] = u[info[i]];
+        }
+        if (!x) {
+            __syncthreads();
+            continue;
+        }
         for (int b = 0; b < n; ++b) {
             __syncthreads();
             for (int p = tid; p < N / 2; p += blockDim.x) {
@@ -53,11 +63,11 @@ k_encode(const uint8_t *msg, uint8_t *x, int64_t F, int N, int n, int K, int kms
     }
 }
 
-int launch_encode(const pc_code *c, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
+int launch_encode(const pc_code *c, const uint8_t *d_msg, uint8_t *d_x, uint8_t *d_ua, int64_t F,
                   hipStream_t stream) {
     int64_t grid = std::min<int64_t>(F, (int64_t)device_cu_count() * 8);
     hipLaunchKernelGGL(k_encode, dim3((unsigned)grid), dim3(256), (size_t)c->N, stream, d_msg, d_x,
-                       F, c->N, c->n, c->K, c->K_msg, c->crc_width, c->d.info,
+                       d_ua, F, c->N, c->n, c->K, c->K_msg, c->crc_width, c->d.info,
                        c->d.crc_of_msg_bit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode launch");

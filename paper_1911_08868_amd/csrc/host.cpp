@@ -46,51 +46,56 @@ int device_cu_count() {
     return cached[dev];
 }
 
-// Library-owned ring of queue counters, one ring per device.  Each decode
-// call takes the next counter and resets it with a one-thread kernel on its
-// own stream before the decode launch, so calls in flight on different
-// streams use different counters unless more than kRing of them overlap.
-static constexpr int kRing = 4096;
+// Library-owned queue counters, per device: blocks of kBlockLines 64-byte
+// lines (one counter per line).  An eager call takes the next block of a
+// ring of kRing blocks and resets it with a kernel on its own stream before
+// its decode launch, so eager calls in flight on different streams use
+// different counters unless more than kRing of them overlap.  A call made
+// while its stream is being captured into a HIP graph takes a block that is
+// never handed out again: the graph may be replayed at any time, beside any
+// later eager call or another graph.  Both regions are allocated by the first
+// call on the device (which must not be under capture).
+static constexpr int kRing = 1024, kHeld = 1024, kBlockLines = 16;
 
-__global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
-// the counters of a block of queues, one per 64-byte line
 __global__ void k_reset_queues(uint32_t *c, int k) {
     if ((int)threadIdx.x < k) c[16 * threadIdx.x] = 0u;
 }
 
-uint32_t *next_counter(int device) {
+uint32_t *counter_block(int device, hipStream_t stream) {
     static std::mutex mu;
-    static uint32_t *ring[64] = {nullptr};
-    static unsigned pos[64] = {0};
-    std::lock_guard<std::mutex> lk(mu);
-    if (device < 0 || device >= 64) return nullptr;
-    if (!ring[device]) {
-        void *p = nullptr;
-        if (hipMalloc(&p, kRing * 64) != hipSuccess) return nullptr;  // one counter per 64 B line
-        ring[device] = static_cast<uint32_t *>(p);
+    static uint32_t *base[64] = {nullptr};
+    static unsigned ring_pos[64] = {0}, held_used[64] = {0};
+    if (device < 0 || device >= 64) {
+        set_error("device index out of range");
+        return nullptr;
     }
-    uint32_t *c = ring[device] + (size_t)(pos[device] % kRing) * 16;
-    pos[device]++;
-    return c;
-}
-
-// The same for the k-queue counters of a single-code decode: a ring of blocks
-// of k consecutive 64-byte lines.
-uint32_t *next_queue_block(int device, int k) {
-    static std::mutex mu;
-    static uint32_t *ring[64] = {nullptr};
-    static unsigned pos[64] = {0};
-    constexpr int kBlocks = 1024, kMaxK = 16;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    const bool capturing = cs == hipStreamCaptureStatusActive;
     std::lock_guard<std::mutex> lk(mu);
-    if (device < 0 || device >= 64 || k < 1 || k > kMaxK) return nullptr;
-    if (!ring[device]) {
+    if (!base[device]) {
+        if (capturing) {
+            set_error("the first decode call on a device must not be captured (it allocates the queue counters)");
+            return nullptr;
+        }
         void *p = nullptr;
-        if (hipMalloc(&p, (size_t)kBlocks * kMaxK * 64) != hipSuccess) return nullptr;
-        ring[device] = static_cast<uint32_t *>(p);
+        if (hipMalloc(&p, (size_t)(kRing + kHeld) * kBlockLines * 64) != hipSuccess) {
+            set_error("queue counter allocation");
+            return nullptr;
+        }
+        base[device] = static_cast<uint32_t *>(p);
     }
-    uint32_t *c = ring[device] + (size_t)(pos[device] % kBlocks) * kMaxK * 16;
-    pos[device]++;
-    return c;
+    size_t blk;
+    if (capturing) {
+        if (held_used[device] >= (unsigned)kHeld) {
+            set_error("more than 1024 captured decode calls on this device (each keeps its counters)");
+            return nullptr;
+        }
+        blk = kRing + held_used[device]++;
+    } else {
+        blk = ring_pos[device]++ % kRing;
+    }
+    return base[device] + blk * kBlockLines * 16;
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +305,16 @@ int polar_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_
     if (F < 0) return fail(PC_EINVAL, "F < 0");
     if (F == 0) return PC_OK;
     if (!d_msg || !d_x) return fail(PC_EINVAL, "null buffer");
-    return launch_encode(code, d_msg, d_x, F, static_cast<hipStream_t>(stream));
+    return launch_encode(code, d_msg, d_x, nullptr, F, static_cast<hipStream_t>(stream));
+}
+
+int polar_info_bits(const pc_code *code, const uint8_t *d_msg, uint8_t *d_u_info, int64_t F,
+                    void *stream) {
+    if (!code) return fail(PC_EINVAL, "code is NULL");
+    if (F < 0) return fail(PC_EINVAL, "F < 0");
+    if (F == 0) return PC_OK;
+    if (!d_msg || !d_u_info) return fail(PC_EINVAL, "null buffer");
+    return launch_encode(code, d_msg, nullptr, d_u_info, F, static_cast<hipStream_t>(stream));
 }
 
 static int check_bp(const pc_code *code, const pc_bp_params *bp) {
@@ -359,9 +373,9 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     } else {
         for (int s = 0; s < n; ++s) orders[s] = (int8_t)s;
     }
-    uint32_t *ctr = next_queue_block(code->device, kQueues);
-    if (!ctr) return fail(PC_ENOMEM, "queue counter allocation");
     hipStream_t hs = static_cast<hipStream_t>(stream);
+    uint32_t *ctr = counter_block(code->device, hs);
+    if (!ctr) return PC_ENOMEM;
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, hs, ctr, kQueues);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");

@@ -52,9 +52,11 @@ int make_pool(int n, int k, int Q, uint64_t seed, int8_t *orders);
 // number of compute units of the current device (cached)
 int device_cu_count();
 
-// per-call queue counter in a library-owned device ring
-uint32_t *next_counter(int device);
-uint32_t *next_queue_block(int device, int k);
+// per-call queue counters (16 lines of 64 bytes, one counter per line) from
+// library-owned device memory: a recycled ring for eager calls, a block kept
+// for good for a call under graph capture; NULL (error set) on failure
+uint32_t *counter_block(int device, hipStream_t stream);
+__global__ void k_reset_queues(uint32_t *c, int k);
 
 // ---- decode ----------------------------------------------------------------
 struct DecodeConfig {
@@ -69,7 +71,9 @@ int launch_decode(const pc_code *code, const float *d_llr, int64_t F, const pc_b
                   int32_t *d_iters, uint8_t *d_ok, float *d_soft, const pc_launch_cfg *cfg,
                   hipStream_t stream);
 
-int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, int64_t F,
+// x = u G_N into d_x (or NULL), and u on the information rows into d_ua
+// [F][K] (or NULL)
+int launch_encode(const pc_code *code, const uint8_t *d_msg, uint8_t *d_x, uint8_t *d_ua, int64_t F,
                   hipStream_t stream);
 
 // Algorithm 1 with random subgraphs (per-row stage orders, messages in LDS)

@@ -17,7 +17,9 @@ static int stub(const char *what) {
     return PC_ENOTSUP;
 }
 int launch_decode_n(int, const DecodeLaunch &) { return stub("decode"); }
-int launch_encode(const pc_code *, const uint8_t *, uint8_t *, int64_t, hipStream_t) { return stub("encode"); }
+int launch_encode(const pc_code *, const uint8_t *, uint8_t *, uint8_t *, int64_t, hipStream_t) {
+    return stub("encode");
+}
 int launch_alg1(const pc_code *, const float *, int64_t, const pc_bp_params &, const pc_pp_params &, uint8_t *,
                 int32_t *, uint8_t *, float *, uint64_t *, int32_t, hipStream_t) {
     return stub("alg1");
@@ -74,6 +76,7 @@ int main() {
     EXPECT(bp_decode(nullptr, nullptr, 1, &bp, nullptr, nullptr, nullptr, nullptr) == PC_EINVAL);
     EXPECT(pp_mt_bp_decode(nullptr, nullptr, 1, &bp, &pp, nullptr, nullptr, nullptr, nullptr) == PC_EINVAL);
     EXPECT(polar_encode(nullptr, nullptr, nullptr, 1, nullptr) == PC_EINVAL);
+    EXPECT(polar_info_bits(nullptr, nullptr, nullptr, 1, nullptr) == PC_EINVAL);
     EXPECT(pp_mt_bp_decode_trace(nullptr, nullptr, 1, &bp, &pp, nullptr, nullptr, nullptr, nullptr, 0, nullptr) ==
            PC_EINVAL);
     EXPECT(polar_classify_errors(nullptr, nullptr, nullptr, nullptr, nullptr, 8, 4, 4, nullptr, nullptr, nullptr) ==

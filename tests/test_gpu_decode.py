@@ -91,10 +91,14 @@ def test_encoder_bit_exact(orc, pbp, N, K, cw, poly):
     code = gpu_code(pbp, oc)
     for F in (1, 37, 1000):
         msg = synth.message_bits(N + F, F, oc.K_msg)
-        _, x = orc.encode(oc, msg)
-        got = pbp.encode(code, torch.from_numpy(msg).cuda())
+        u, x = orc.encode(oc, msg)
+        d_msg = torch.from_numpy(msg).cuda()
+        got = pbp.encode(code, d_msg)
+        ua = pbp.info_bits(code, d_msg)
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), x)
+        # u on the information rows: the message, then its CRC
+        assert np.array_equal(ua.cpu().numpy(), u[:, oc.info_idx])
 
 
 @pytest.mark.parametrize("snr", [1.0, 2.0, 3.0, 4.0])
@@ -354,3 +358,84 @@ def test_decode_graph_replays(orc, pbp):
                 assert torch.equal(a, b), f"replay {rep} differs"
             assert int(got[1].min().item()) >= 1
             _ = (base * 2).sum().item()  # eager work between replays
+
+
+def test_c_entry_points_called_directly(orc, pbp):
+    """bp_decode and pp_mt_bp_decode called through their own C symbols (not
+    the _ex entry point the Python wrappers use), with NULL and with real
+    iteration and verdict buffers, against the oracle frame by frame."""
+    import ctypes
+    torch = _torch()
+    oc, msg, llr = frames(orc, 256, 144, 16, 0x1021, 300, 2.0, seed=41)
+    code = gpu_code(pbp, oc)
+    L = pbp.lib()
+    d_llr = torch.from_numpy(llr).cuda()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    bp = pbp.BPParams(max_iter=100, stop=pbp.STOP_CRC, it_min=3)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=3, period_T=7, pool_Q=6, seed=5)
+    ref_bp = orc.decode(oc, llr, orc.DecodeParams(max_iter=100, stop=orc.STOP_CRC, it_min=3), threads=8)
+    ref_pp = orc.decode(oc, llr, orc.DecodeParams(max_iter=100, stop=orc.STOP_CRC, it_min=3,
+                                                  pp_mode=orc.PP_LASTK, k=3, T=7, Q=6, seed=5),
+                        threads=8)
+    for with_out in (False, True):
+        for name, ref in (("bp_decode", ref_bp), ("pp_mt_bp_decode", ref_pp)):
+            m = torch.full((300, oc.K_msg), 9, dtype=torch.uint8, device="cuda")
+            it = torch.full((300,), -1, dtype=torch.int32, device="cuda") if with_out else None
+            ok = torch.full((300,), 9, dtype=torch.uint8, device="cuda") if with_out else None
+            bpc, ppc = bp.c(), pp.c()
+            if name == "bp_decode":
+                rc = L.bp_decode(code.handle, P(d_llr), 300, ctypes.byref(bpc), P(m), P(it), P(ok), stream)
+            else:
+                rc = L.pp_mt_bp_decode(code.handle, P(d_llr), 300, ctypes.byref(bpc), ctypes.byref(ppc),
+                                       P(m), P(it), P(ok), stream)
+            assert rc == 0, L.polar_last_error()
+            torch.cuda.synchronize()
+            assert np.array_equal(m.cpu().numpy(), ref.msg_hat), name
+            if with_out:
+                assert np.array_equal(it.cpu().numpy(), ref.iters), name
+                assert np.array_equal(ok.cpu().numpy(), ref.ok), name
+    assert not np.array_equal(ref_bp.iters, ref_pp.iters)   # the schedules differ on these frames
+
+
+def test_captured_decode_keeps_its_counters(orc, pbp):
+    """A decode captured into a HIP graph keeps its queue counters: after
+    1023 further eager calls (a full turn of the counter ring), the graph is
+    replayed on one stream while an eager decode of other frames runs on a
+    second stream, and each output equals a separate eager run."""
+    torch = _torch()
+    oc, msg, llr = frames(orc, 1024, 512, 16, 0x1021, 6000, 2.0, seed=43)
+    _, _, llr2 = frames(orc, 1024, 512, 16, 0x1021, 6000, 2.25, seed=44)
+    code = gpu_code(pbp, oc)
+    bp = pbp.BPParams(max_iter=100, stop=pbp.STOP_CRC, it_min=3)
+    pp = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
+    a_llr, b_llr = torch.from_numpy(llr).cuda(), torch.from_numpy(llr2).cuda()
+    mk = lambda: (torch.empty((6000, oc.K_msg), dtype=torch.uint8, device="cuda"),
+                  torch.empty(6000, dtype=torch.int32, device="cuda"),
+                  torch.empty(6000, dtype=torch.uint8, device="cuda"))
+    a_out, b_out, a_ref, b_ref = mk(), mk(), mk(), mk()
+    pbp.pp_mt_bp_decode(code, a_llr, bp, pp, out=a_ref)
+    pbp.pp_mt_bp_decode(code, b_llr, bp, pp, out=b_ref)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pbp.pp_mt_bp_decode(code, a_llr, bp, pp, out=a_out)
+    torch.cuda.synchronize()
+    small = torch.from_numpy(llr[:4]).cuda()
+    sm = (torch.empty((4, oc.K_msg), dtype=torch.uint8, device="cuda"),
+          torch.empty(4, dtype=torch.int32, device="cuda"), torch.empty(4, dtype=torch.uint8, device="cuda"))
+    for _ in range(1023):
+        pbp.pp_mt_bp_decode(code, small, bp, pp, out=sm)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    for t in a_out + b_out:
+        t.zero_()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sa):
+        g.replay()
+    with torch.cuda.stream(sb):
+        pbp.pp_mt_bp_decode(code, b_llr, bp, pp, out=b_out)
+    torch.cuda.synchronize()
+    for got, ref, what in ((a_out, a_ref, "graph replay"), (b_out, b_ref, "eager call")):
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), what
