@@ -260,6 +260,25 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
                             uint8_t *d_ok, void *d_ws, size_t ws_bytes,
                             const pc_launch_cfg *cfg, void *stream);
 
+/* pp_mt_bp_decode_batched without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture without a warm-up call, serving loops, harnesses that
+ * forbid hipMalloc).  The queue control words and frame list live in a
+ * library-owned scratch of 4 MiB + 256 bytes per device (a static device
+ * array, resolved once per device by polar_construct or by the first call),
+ * so F may not exceed 1048576 (PC_EINVAL otherwise); the codes' device must
+ * be current.  Every call on a device shares that device's scratch and
+ * clears what it needs with its own kernels: calls that overlap on one
+ * device (other streams, or graphs replayed beside each other) race and give
+ * undefined results; serialise them.  Other arguments and results as
+ * pp_mt_bp_decode_batched, whose kernels it runs.                          */
+int pp_mt_bp_decode_batched_noalloc(const pc_code *const *codes, int32_t n_codes,
+                                    const int32_t *d_code_id, const int64_t *d_llr_off,
+                                    const float *d_llr_pool, int64_t F, const pc_bp_params *bp,
+                                    const pc_pp_params *pp, uint8_t *d_bits_pool,
+                                    const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok,
+                                    const pc_launch_cfg *cfg, void *stream);
+
 /* Weighted BP: the unrolled decoder with a learnable scale on every check-node
  * output, w[t][s-1][d][row] (iteration t, stage s, d = 0 L sweep / 1 R sweep,
  * output row), frozen prior 2^60, no early stop, T_unroll iterations; the

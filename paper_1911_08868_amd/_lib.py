@@ -18,6 +18,7 @@ EXPORTS = [
     "polar_batched_workspace_bytes", "pp_mt_bp_decode_batched", "wbp_workspace_bytes",
     "wbp_forward", "wbp_backward", "polar_strerror", "polar_last_error",
     "pp_mt_bp_decode_trace", "polar_classify_errors", "polar_info_bits",
+    "pp_mt_bp_decode_batched_noalloc",
 ]
 CHECK_MINSUM, CHECK_EXACT = 0, 1
 ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED = 0, 1, 2, 3
@@ -89,6 +90,8 @@ def lib() -> ctypes.CDLL:
         "polar_batched_workspace_bytes": ([i64], sz),
         "pp_mt_bp_decode_batched": ([vp, i32, vp, vp, vp, i64, P(BPParamsC), P(PPParamsC),
                                      vp, vp, vp, vp, vp, sz, P(LaunchCfgC), vp], ctypes.c_int),
+        "pp_mt_bp_decode_batched_noalloc": ([vp, i32, vp, vp, vp, i64, P(BPParamsC), P(PPParamsC),
+                                             vp, vp, vp, vp, P(LaunchCfgC), vp], ctypes.c_int),
         "wbp_workspace_bytes": ([vp, i64, i32], sz),
         "wbp_forward": ([vp, vp, i64, vp, i32, P(PPParamsC), vp, vp, sz, vp], ctypes.c_int),
         "wbp_backward": ([vp, vp, i64, vp, i32, P(PPParamsC), vp, vp, vp, sz, vp],

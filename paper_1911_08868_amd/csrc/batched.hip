@@ -228,6 +228,43 @@ static int launch_batched_rho(const BatchedArgs &a, int rho, int block, int grid
 
 size_t batched_ws_bytes(int64_t F) { return 256 + (size_t)std::max<int64_t>(F, 1) * sizeof(int32_t); }
 
+// Scratch of the allocation-free batched entry point: the queue control
+// words and the frame list of one call, for at most kNoAllocMaxFrames frames
+// (4 MiB + 256 bytes, held by every device the library runs on until the
+// process ends).  Host code never passes `scratch` itself to a kernel: its
+// name is a host-side stand-in, and the device address of each device's copy
+// comes from hipGetSymbolAddress with that device current.
+constexpr int64_t kNoAllocMaxFrames = int64_t(1) << 20;
+constexpr size_t kNoAllocBytes = 256 + (size_t)kNoAllocMaxFrames * sizeof(int32_t);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {nullptr};
+
+// Resolve the current device's copy of the scratch (once per device).
+// Called by polar_construct, and by the entry point if a call comes first on
+// a device that constructed nothing.  Returns PC_OK or PC_EHIP.
+int noalloc_scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(PC_ENOTSUP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return PC_OK;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PC_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[dev] = p;
+    return PC_OK;
+}
+
+static void *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace pbp
 
 using namespace pbp;
@@ -236,11 +273,13 @@ extern "C" {
 
 size_t polar_batched_workspace_bytes(int64_t F) { return F < 0 ? 0 : batched_ws_bytes(F); }
 
-int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
-                            const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
-                            const pc_bp_params *bp, const pc_pp_params *pp, uint8_t *d_bits_pool,
-                            const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok, void *d_ws,
-                            size_t ws_bytes, const pc_launch_cfg *cfg, void *stream) {
+}  // extern "C"
+
+static int decode_batched_impl(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
+                               const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
+                               const pc_bp_params *bp, const pc_pp_params *pp, uint8_t *d_bits_pool,
+                               const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok, void *d_ws,
+                               size_t ws_bytes, const pc_launch_cfg *cfg, void *stream) {
     if (!codes || n_codes < 1 || n_codes > kBatchMaxCodes) return fail(PC_EINVAL, "need 1..32 codes");
     if (!bp) return fail(PC_EINVAL, "bp params are NULL");
     if (F < 0 || F > INT32_MAX) return fail(PC_EINVAL, "F must be in [0, 2^31)");
@@ -320,6 +359,43 @@ int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const 
                            : launch_batched_rho<4, false>(a, rho, block, grid, s);
     return sc ? launch_batched_rho<0, true>(a, rho, block, grid, s)
               : launch_batched_rho<0, false>(a, rho, block, grid, s);
+}
+
+extern "C" {
+
+int pp_mt_bp_decode_batched(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
+                            const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
+                            const pc_bp_params *bp, const pc_pp_params *pp, uint8_t *d_bits_pool,
+                            const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok, void *d_ws,
+                            size_t ws_bytes, const pc_launch_cfg *cfg, void *stream) {
+    return decode_batched_impl(codes, n_codes, d_code_id, d_llr_off, d_llr_pool, F, bp, pp, d_bits_pool,
+                               d_bits_off, d_iters, d_ok, d_ws, ws_bytes, cfg, stream);
+}
+
+int pp_mt_bp_decode_batched_noalloc(const pc_code *const *codes, int32_t n_codes, const int32_t *d_code_id,
+                                    const int64_t *d_llr_off, const float *d_llr_pool, int64_t F,
+                                    const pc_bp_params *bp, const pc_pp_params *pp, uint8_t *d_bits_pool,
+                                    const int64_t *d_bits_off, int32_t *d_iters, uint8_t *d_ok,
+                                    const pc_launch_cfg *cfg, void *stream) {
+    if (F > kNoAllocMaxFrames)
+        return fail(PC_EINVAL, "pp_mt_bp_decode_batched_noalloc takes at most 1048576 frames per call");
+    if (F <= 0 || !codes || n_codes < 1)
+        return decode_batched_impl(codes, n_codes, d_code_id, d_llr_off, d_llr_pool, F, bp, pp, d_bits_pool,
+                                   d_bits_off, d_iters, d_ok, nullptr, 0, cfg, stream);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (int i = 0; i < n_codes; ++i)
+        if (codes[i] && codes[i]->device != dev)
+            return fail(PC_EINVAL, "the codes' device must be current (the scratch is per device)");
+    void *ws = noalloc_scratch(dev);
+    if (!ws) {
+        const int rc = noalloc_scratch_init();
+        if (rc != PC_OK) return rc;
+        ws = noalloc_scratch(dev);
+    }
+    return decode_batched_impl(codes, n_codes, d_code_id, d_llr_off, d_llr_pool, F, bp, pp, d_bits_pool,
+                               d_bits_off, d_iters, d_ok, ws, kNoAllocBytes, cfg, stream);
 }
 
 }  // extern "C"

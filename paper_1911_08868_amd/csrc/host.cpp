@@ -278,6 +278,10 @@ int polar_construct(int32_t N, int32_t K, int32_t crc_width, uint32_t crc_poly,
         delete c;
         return rc;
     }
+    // per-device set-up of the allocation-free batched entry point: the
+    // address of this device's scratch (a failure here is reported by that
+    // entry point, which resolves it again)
+    (void)noalloc_scratch_init();
     *out = c;
     return PC_OK;
 }

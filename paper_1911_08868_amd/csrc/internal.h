@@ -87,6 +87,9 @@ int launch_classify(const uint8_t *d_msg_hat, const uint8_t *d_msg, const uint8_
                     int32_t K_msg, uint8_t *d_class, int32_t *d_period, hipStream_t stream);
 
 size_t batched_ws_bytes(int64_t F);
+// resolve the current device's copy of the allocation-free entry point's
+// scratch (batched.hip); PC_OK or PC_EHIP
+int noalloc_scratch_init();
 
 size_t wbp_ws_bytes(const pc_code *code, int64_t F, int T);
 int launch_wbp_forward(const pc_code *code, const float *d_llr, int64_t F, const float *d_w,

@@ -24,6 +24,7 @@ int launch_alg1(const pc_code *, const float *, int64_t, const pc_bp_params &, c
                 int32_t *, uint8_t *, float *, uint64_t *, int32_t, hipStream_t) {
     return stub("alg1");
 }
+int noalloc_scratch_init() { return PC_EHIP; }
 int launch_classify(const uint8_t *, const uint8_t *, const uint8_t *, const int32_t *, const uint64_t *, int32_t,
                     int64_t, int32_t, uint8_t *, int32_t *, hipStream_t) {
     return stub("classify");
