@@ -33,11 +33,15 @@ SNRS = [1.5 + 0.25 * i for i in range(9)]
 MAX_ITER, IT_MIN = 200, 3
 PP_K, PP_T, PP_Q, PP_SEED = 4, 10, 8, 1
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one non-packed 32-bit VALU
-# operation per lane per clock (the 157.3 TFLOP/s fp32 figure counts packed FMA
-# as 4 flops per lane-clock)
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 128 B/clk/CU
+# MI355X VALU issue rates per CU and clock (four SIMDs): FP32 add, mul, fma and
+# 32-bit bitwise operations 128 lanes (the 157.3 TFLOP/s FP32 vector figure is
+# 256 CUs x 2.4 GHz x 128 FMA lanes x 2 flops), v_med3_f32 64 lanes (half rate;
+# both measured with per-instruction probes).  A processing element issues 2
+# v_add_f32, 2 v_med3_f32 and 2 v_bitop3_b32: 2/64 + 4/128 = 1/16 CU-clock per
+# lane, 96 of its lane-ops per CU-clock.  The roofline takes the larger of this
+# figure and the calibration kernel's measured rate for the same mix.
+PE_OPS_PER_CU_CLK = 6 / (2 / 64 + 4 / 128)
+ALU_PEAK_TOPS = 256 * PE_OPS_PER_CU_CLK * 2.4e9 / 1e12
 
 
 def parse():
@@ -54,7 +58,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
     ap.add_argument("--extra", type=str, default="",
-                    help="only run one side workload of paper_1911_08868_amd.workloads "
+                    help="only run one side workload of bench_workloads.py "
                          "(e.g. exact_boxplus, error_classes) and print its JSON")
     ap.add_argument("--extra-frames", type=int, default=0,
                     help="frames per point for --extra (0: the workload's default)")
@@ -71,6 +75,42 @@ def calib_copy(torch):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"calib_copy_bytes": 2 ** 30, "copies": 4}), flush=True)
+
+
+def calibrate(torch):
+    """Measured roofline constants: the VALU issue rate of the decoder's
+    instruction mix (add, v_med3_f32, v_bitop3_b32; 48 per loop trip) and the
+    LDS read bandwidth (conflict-free 16-byte reads), from the kernels of
+    libpbp_peak.so, each timed with HIP events on torch's stream."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1911_08868_amd", "libpbp_peak.so")
+    L = ctypes.CDLL(path)
+    L.pbp_peak_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.pbp_peak_launch.restype = ctypes.c_int
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for which, blocks, threads, steps in ((0, 256 * 8, 256, 20000), (1, 256 * 2, 1024, 5000)):
+        out = torch.empty(blocks * threads, dtype=torch.int32, device="cuda")
+        ms = []
+        for rep in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rc = L.pbp_peak_launch(which, blocks, steps, ctypes.c_void_p(out.data_ptr()), stream)
+            b.record()
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError(f"calibration kernel {which}: HIP error {rc}")
+            ms.append(a.elapsed_time(b))
+        t = min(ms) / 1e3
+        if which == 0:
+            ops = blocks * 256 * 48 * steps
+            res["valu_lane_ops_per_s"] = ops / t
+            res["valu_frac_of_derived_peak"] = round(ops / t / (ALU_PEAK_TOPS * 1e12), 4)
+        else:
+            byt = blocks * threads * 8 * 16 * steps
+            res["lds_bytes_per_s"] = byt / t
+            res["lds_bytes_per_clk_per_cu"] = round(byt / t / (256 * 2.4e9), 1)
+    return res
 
 
 def kernel_source_hash() -> str:
@@ -120,19 +160,34 @@ def run_decode_set(pbp, code, llrs, outs, bp, pp, torch, events=None, cfg=None):
             events[si][1].record()
 
 
+def cpu_cores():
+    """(threads to use, cores visible): the cores this process may run on,
+    capped at the 16 host cores an MI355X machine assigns to one GPU."""
+    visible = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = visible
+    return max(1, min(16, allowed)), visible, allowed
+
+
 def cpu_baseline(args):
     """The oracle, as is, on a bounded sample of the same workload generated on
-    the host; threads = the host share of cores it actually uses."""
-    import numpy as np
+    the host (same code, decoder and parameters, FP32 mode), one thread per
+    usable host core; also the oracle's frame error rate per Eb/N0 point with
+    its 95% Clopper-Pearson interval, to set beside the GPU's."""
     import oracle
     import synth
-    threads = min(16, os.cpu_count() or 1)
+    from bench_workloads import clopper_pearson
+    threads, visible, allowed = cpu_cores()
     oc = oracle.construct(N, K, DESIGN_DB, CRC_W, CRC_POLY)
     p = oracle.DecodeParams(max_iter=MAX_ITER, stop=oracle.STOP_CRC, it_min=IT_MIN,
                             pp_mode=oracle.PP_LASTK, k=PP_K, T=PP_T, Q=PP_Q, seed=PP_SEED,
                             fp32=True)
     per = 16 * threads  # frames per Eb/N0 point in the first round; grown to fill the budget
     total_frames, total_time = 0, 0.0
+    frames = [0] * len(SNRS)
+    errors = [0] * len(SNRS)
     rounds = 0
     while total_time < args.cpu_seconds and rounds < 6:
         for si, snr in enumerate(SNRS):
@@ -140,20 +195,59 @@ def cpu_baseline(args):
             _, x = oracle.encode(oc, msg)
             llr = synth.awgn_llr(x, snr, K_MSG, seed=2000 + rounds * 31 + si)
             t0 = time.perf_counter()
-            oracle.decode(oc, llr, p, threads=threads)
+            r = oracle.decode(oc, llr, p, threads=threads)
             total_time += time.perf_counter() - t0
             total_frames += per
+            frames[si] += per
+            errors[si] += int((r.msg_hat != msg).any(1).sum())
         rounds += 1
         if total_time < args.cpu_seconds / 4:
             per *= 4
     gbps = total_frames * K_MSG / total_time / 1e9
+    fer = [{"ebn0_db": snr, "frames": f, "frame_errors": e, "fer": e / f, "ci95": clopper_pearson(e, f)}
+           for snr, f, e in zip(SNRS, frames, errors)]
     return {"value": gbps, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
             "sample": f"{total_frames} frames spread evenly over the 9 Eb/N0 points "
-                      f"(same code, decoder and parameters), FP32 mode, {total_time:.1f} s"}
+                      f"(same code, decoder and parameters), FP32 mode, {total_time:.1f} s",
+            "host_cores": {"visible": visible, "affinity": allowed, "used": threads},
+            "fer": fer}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lastk_variants(pbp, code, llrs, msgs, bp, cfg, torch, alu_peak):
+    """PP-MT-BP with the last k in {3, 4, 5} of the 10 stages re-ordered
+    every T in {5, 10} iterations (Q = 8 trellises), on the headline frames,
+    each with its decoded Gbit/s and the decode kernel's ALU roofline
+    fraction (same algorithmic count as the headline)."""
+    F = llrs[0].shape[0]
+    out = {}
+    for k in (3, 4, 5):
+        for T in (5, 10):
+            pp = pbp.PPParams(mode=pbp.PP_LASTK, k=k, period_T=T, pool_Q=PP_Q, seed=PP_SEED)
+            ox = [(torch.empty((F, K_MSG), dtype=torch.uint8, device="cuda"),
+                   torch.empty(F, dtype=torch.int32, device="cuda"),
+                   torch.empty(F, dtype=torch.uint8, device="cuda")) for _ in SNRS]
+            run_decode_set(pbp, code, llrs, ox, bp, pp, torch, cfg=cfg)
+            torch.cuda.synchronize()
+            ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in SNRS]
+            run_decode_set(pbp, code, llrs, ox, bp, pp, torch, events=ev, cfg=cfg)
+            torch.cuda.synchronize()
+            ms = sum(a.elapsed_time(b) for a, b in ev)
+            ops = sum(alg_ops(o[1]) for o in ox)
+            achieved = ops / (ms / 1e3) / 1e12
+            out[f"k{k}_T{T}"] = {
+                "gbit_s": round(len(SNRS) * F * K_MSG / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
+                "roofline": {"bound": "alu", "kernel": f"k_decode<n=10,k={k},rho={cfg.rho}>",
+                             "achieved": round(achieved, 3), "peak": round(alu_peak, 2),
+                             "unit": "TOP/s", "frac": round(achieved / alu_peak, 4)},
+                "fer": [(o[0] != m).any(1).double().mean().item() for o, m in zip(ox, msgs)],
+                "avg_iters": [round(o[1].double().mean().item(), 3) for o in ox]}
+            log(f"last-{k} every {T}: {ms:.1f} ms, {out[f'k{k}_T{T}']['roofline']['frac']} of the ALU peak")
+            del ox
+    return out
 
 
 def main():
@@ -171,9 +265,9 @@ def main():
         calib_copy(torch)
         return
     if args.extra:
-        from paper_1911_08868_amd import workloads
+        import bench_workloads
         kw = {"F": args.extra_frames} if args.extra_frames else {}
-        print(json.dumps(getattr(workloads, args.extra)(torch, pbp, **kw)), flush=True)
+        print(json.dumps(getattr(bench_workloads, args.extra)(torch, pbp, **kw)), flush=True)
         return
     code = pbp.Code(N, K, CRC_W, CRC_POLY, DESIGN_DB)
     F = args.frames
@@ -193,6 +287,12 @@ def main():
                                           path=os.path.join("/tmp", "polarbp_tuned.json"),
                                           force=True)
     log(f"tuned launch shape rho={cfg.rho} slots={cfg.slots}: {tuned['all']}")
+    cal = calibrate(torch)
+    alu_peak = max(ALU_PEAK_TOPS, cal["valu_lane_ops_per_s"] / 1e12)
+    log(f"calibration: the processing element's VALU mix at {cal['valu_lane_ops_per_s'] / 1e12:.2f} T lane-ops/s "
+        f"({cal['valu_frac_of_derived_peak']} of the derived {ALU_PEAK_TOPS:.2f}), "
+        f"LDS {cal['lds_bytes_per_clk_per_cu']} B/clk/CU; ALU peak taken {alu_peak:.2f} T lane-ops/s")
+    lds_peak = cal["lds_bytes_per_s"] / 1e12
 
     for w in range(args.warmup):
         run_decode_set(pbp, code, llrs, outs, bp, pp, torch, cfg=cfg)
@@ -236,15 +336,21 @@ def main():
     # into groups of at most rho stages
     boundaries = -(-(10 - PP_K) // cfg.rho) + -(-PP_K // cfg.rho) - 1
     lds_bytes_per_it = boundaries * 4 * 4 * N  # (L, R) x (written, read) x N x 4 B per boundary
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
-            "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(alu_peak, 2),
+            "unit": "TOP/s", "frac": round(achieved / alu_peak, 4), "traffic": None,
             "kernel": f"k_decode<n=10,k=4,rho={cfg.rho}>", "launch": {"rho": cfg.rho, "slots": cfg.slots,
                                                                    "tuned_ms": tuned["all"]},
             "ops_per_frame_iteration": 3 * N * (10 + 9),
             "launch_ms_avg": round(launch_ms / len(SNRS), 3),
             "lds": {"bytes_per_frame_iteration": lds_bytes_per_it,
                     "achieved_TBs": round(lds_bytes_per_it * it_total / (launch_ms / 1e3) / 1e12, 3),
-                    "peak_TBs": round(LDS_PEAK_TBS, 2)},
+                    "peak_TBs": round(lds_peak, 2), "peak_source": "measured (calibration)"},
+            "peak_basis": f"max(derived {ALU_PEAK_TOPS:.2f}: 256 CUs x 2.4 GHz x 96 lane-ops of the processing "
+                          f"element's mix per CU-clock, measured calibration)",
+            "calibration": {"valu_TOPs": round(cal["valu_lane_ops_per_s"] / 1e12, 3),
+                            "valu_frac_of_derived_peak": cal["valu_frac_of_derived_peak"],
+                            "lds_TBs": round(lds_peak, 2),
+                            "lds_bytes_per_clk_per_cu": cal["lds_bytes_per_clk_per_cu"]},
             "source_hash": kernel_source_hash()}
     prof = os.path.join(ROOT, "profiles", "k_decode_n1024_traffic.json")
     if os.path.exists(prof):
@@ -279,11 +385,15 @@ def main():
                                     for o, m in zip(ox, msgs)],
                             "avg_iters": [round(o[1].double().mean().item(), 3) for o in ox]}
             del ox
+        # the other schedules of the same configuration: last k in {3, 4, 5}
+        # stages every T in {5, 10} iterations (Q = 8), on the same frames
+        extras["lastk_variants"] = lastk_variants(pbp, code, llrs, msgs, bp, cfg, torch, alu_peak)
         del llrs, outs
         torch.cuda.empty_cache()
         try:
-            from paper_1911_08868_amd import workloads
-            extras.update(workloads.bench_extras(torch, pbp))
+            import bench_workloads
+            bench_workloads.ALU_PEAK = alu_peak * 1e12
+            extras.update(bench_workloads.bench_extras(torch, pbp))
         except ImportError as e:
             extras["weighted_bp"] = None
             extras["batched_mixed"] = None
@@ -306,6 +416,12 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args)
+        # the oracle's frame error rate and interval beside the GPU's, per point
+        for row, o in zip(per_snr, out["cpu_baseline"]["fer"]):
+            row["oracle_fer"] = o["fer"]
+            row["oracle_frames"] = o["frames"]
+            row["oracle_ci95"] = [round(x, 6) for x in o["ci95"]]
+            row["gpu_fer_in_oracle_ci95"] = bool(o["ci95"][0] <= row["fer"] <= o["ci95"][1])
     print(json.dumps(out), flush=True)
 
 

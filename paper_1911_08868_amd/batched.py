@@ -8,19 +8,12 @@ preparation kernels and the persistent decoder -- into a torch CUDA graph
 data the buffers hold.  No memset nodes are recorded: the library clears its
 counters with a kernel.
 
-``make_mixed_stream`` draws the mixed workload (code per frame, Eb/N0 per
-frame, message bits) and fills a round with encoded, AWGN-corrupted frames;
-``bench_mixed`` times rounds of it for bench.py.
+The mixed workload that bench.py times lives beside it
+(``bench_workloads.py``).
 """
 from __future__ import annotations
 
-import sys
-
 from . import api
-
-
-def _log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 # the mixed stream: 4 block lengths x 5 rates, CRC-16, K counts the CRC
@@ -84,102 +77,3 @@ class BatchedDecoder:
 
     def replay(self):
         self.graph.replay()
-
-
-def make_mixed_stream(torch, dec: BatchedDecoder, seed: int, lo_db=1.0, hi_db=4.0):
-    """Fill a round: code uniform over dec.codes, Eb/N0 uniform on [lo, hi] dB
-    per frame, uniform message bits; encoded on the GPU, BPSK over AWGN.
-    Returns the messages per code group for error counting."""
-    import synth
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    F = dec.F
-    cid = torch.randint(0, len(dec.codes), (F,), generator=gen, device="cuda")
-    dec.set_layout(cid)
-    ebn0 = torch.rand(F, generator=gen, device="cuda", dtype=torch.float64) * (hi_db - lo_db) + lo_db
-    groups = []
-    for c_i, code in enumerate(dec.codes):
-        idx = torch.nonzero(cid == c_i).flatten()
-        if idx.numel() == 0:
-            groups.append((idx, None))
-            continue
-        m = torch.randint(0, 2, (idx.numel(), code.K_msg), generator=gen, device="cuda",
-                          dtype=torch.uint8)
-        x = api.encode(code, m)
-        llr = synth.awgn_llr_torch(x, ebn0[idx], code.K_msg, gen)
-        # scatter the frames into the pool
-        off = dec.llr_off[idx]
-        cols = torch.arange(code.N, device="cuda")
-        dec.llr_pool[(off[:, None] + cols[None, :]).flatten()] = llr.flatten()
-        groups.append((idx, m))
-    torch.cuda.synchronize()
-    return groups
-
-
-def frame_errors(torch, dec: BatchedDecoder, groups):
-    errs = 0
-    for c_i, (idx, m) in enumerate(groups):
-        if m is None:
-            continue
-        code = dec.codes[c_i]
-        off = dec.bits_off[idx]
-        cols = torch.arange(code.K_msg, device="cuda")
-        got = dec.bits_pool[(off[:, None] + cols[None, :])]
-        errs += int((got != m).any(1).sum().item())
-    return errs
-
-
-def bench_mixed(torch, pbp, frames_total=4_000_000, rounds=4, cfg=None):
-    """The mixed-length stream: frames_total frames in `rounds` graph-captured
-    rounds.  Throughput counts decoded message bits of every frame."""
-    bp = api.BPParams(max_iter=200, stop=api.STOP_CRC, it_min=3)
-    pp = api.PPParams(mode=api.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
-    codes = mixed_codes()
-    F = frames_total // rounds
-    decs, groups = [], []
-    for r in range(rounds):
-        d = BatchedDecoder(codes, F, bp, pp, cfg)
-        groups.append(make_mixed_stream(torch, d, seed=500 + r))
-        if r == 0 and cfg is None:
-            from .tune import tune_batched
-            cfg, tuned = tune_batched(torch, d, path="/tmp/polarbp_tuned.json", force=True)
-            _log(f"mixed stream tuned launch shape {tuned['all']}")
-        d.cfg = cfg
-        d.capture()
-        decs.append(d)
-    _log(f"mixed stream: {rounds} captured rounds of {F} frames")
-    for d in decs:
-        d.replay()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for d in decs:
-        d.replay()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
-    bits = sum(int(d.Kmsg[d.code_id.to(torch.int64)].sum().item()) for d in decs)
-    errs = sum(frame_errors(torch, d, g) for d, g in zip(decs, groups))
-    iters = torch.cat([d.iters for d in decs]).double()
-    # algorithmic VALU lane-ops as for the single-length decoder: 6 per
-    # processing element, N/2 per stage, n stages per L sweep and n-1 live
-    # stages per R sweep (the deciding iteration runs no R sweep)
-    ops = 0.0
-    for d in decs:
-        Nf = d.N[d.code_id.to(torch.int64)].double()
-        nf = torch.log2(Nf)
-        it = d.iters.double()
-        ops += (3 * Nf * (nf * it + (nf - 1) * (it - 1))).sum().item()
-    alu_peak = 256 * 64 * 2.4e9
-    _log(f"mixed stream: {ms:.1f} ms")
-    out = {"workload": f"{frames_total} frames, N ~ U{{128,256,512,1024}}, R ~ U{{1/4,1/3,1/2,2/3,3/4}}, "
-                       "CRC-16, Eb/N0 ~ U[1,4] dB, PP-MT-BP k=4 T=10 Q=8, max 200 iterations, "
-                       f"{rounds} hipGraph-captured rounds",
-           "gbit_s": round(bits / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
-           "frames_s": round(frames_total / (ms / 1e3), 1),
-           "avg_iters": round(iters.mean().item(), 3), "fer": errs / frames_total,
-           "alu_frac": round(ops / (ms / 1e3) / alu_peak, 4),
-           "launch": {"rho": cfg.rho, "slots": cfg.slots}}
-    del decs
-    torch.cuda.empty_cache()
-    return out

@@ -47,9 +47,13 @@ class WeightedBP(torch.autograd.Function):
         llr, w = ctx.saved_tensors
         state = ctx.state
         if ctx.ws is None:
-            raise RuntimeError("weighted BP forward ran without checkpoints (keep=False): no backward")
+            raise RuntimeError("weighted BP forward ran without checkpoints (keep=False), or its "
+                               "backward already ran: no backward")
         gw = torch.empty_like(w)
         api.wbp_backward(state.code, llr, w.detach(), state.pp, grad_out.contiguous(), gw, ctx.ws)
+        # the checkpoints serve this one backward: release them now rather
+        # than with the graph, which a caller holding the loss keeps alive
+        ctx.ws = None
         return None, gw, None, None
 
 
