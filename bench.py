@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cfg", type=str, default="",
                     help="launch shape 'rho,slots' (skips the autotuner)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run the VALU and LDS calibration kernels and print their rates")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
     ap.add_argument("--extra", type=str, default="",
@@ -89,7 +91,9 @@ def calibrate(torch):
     L.pbp_peak_launch.restype = ctypes.c_int
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     res = {}
-    for which, blocks, threads, steps in ((0, 256 * 8, 256, 20000), (1, 256 * 2, 1024, 5000)):
+    for which, blocks, threads, steps in ((0, 256 * 8, 256, 20000), (1, 256 * 2, 1024, 5000),
+                                          (2, 256 * 8, 256, 15000), (3, 256 * 8, 256, 15000),
+                                          (4, 256 * 8, 256, 15000)):
         out = torch.empty(blocks * threads, dtype=torch.int32, device="cuda")
         ms = []
         for rep in range(3):
@@ -106,10 +110,14 @@ def calibrate(torch):
             ops = blocks * 256 * 48 * steps
             res["valu_lane_ops_per_s"] = ops / t
             res["valu_frac_of_derived_peak"] = round(ops / t / (ALU_PEAK_TOPS * 1e12), 4)
-        else:
+        elif which == 1:
             byt = blocks * threads * 8 * 16 * steps
             res["lds_bytes_per_s"] = byt / t
             res["lds_bytes_per_clk_per_cu"] = round(byt / t / (256 * 2.4e9), 1)
+        else:
+            name = {2: "v_add_f32", 3: "v_med3_f32", 4: "v_xor_b32"}[which]
+            ops = blocks * threads * 64 * steps
+            res.setdefault("lanes_per_cu_clk", {})[name] = round(ops / t / (256 * 2.4e9), 1)
     return res
 
 
@@ -264,6 +272,9 @@ def main():
     if args.calib_copy:
         calib_copy(torch)
         return
+    if args.calibrate:
+        print(json.dumps(calibrate(torch)), flush=True)
+        return
     if args.extra:
         import bench_workloads
         kw = {"F": args.extra_frames} if args.extra_frames else {}
@@ -350,7 +361,8 @@ def main():
             "calibration": {"valu_TOPs": round(cal["valu_lane_ops_per_s"] / 1e12, 3),
                             "valu_frac_of_derived_peak": cal["valu_frac_of_derived_peak"],
                             "lds_TBs": round(lds_peak, 2),
-                            "lds_bytes_per_clk_per_cu": cal["lds_bytes_per_clk_per_cu"]},
+                            "lds_bytes_per_clk_per_cu": cal["lds_bytes_per_clk_per_cu"],
+                            "lanes_per_cu_clk": cal["lanes_per_cu_clk"]},
             "source_hash": kernel_source_hash()}
     prof = os.path.join(ROOT, "profiles", "k_decode_n1024_traffic.json")
     if os.path.exists(prof):

@@ -35,6 +35,42 @@ __device__ __forceinline__ void half_step(const float (&a)[8], float (&b)[8]) {
     b[7] = pe_like<7>(a);
 }
 
+// One instruction kind alone, eight independent chains, 8 x 8 instructions
+// per loop trip: KIND 0 v_add_f32, 1 v_med3_f32 (bound by the next chain's
+// magnitude), 2 v_bitop3_b32 (the next chain's sign bit xored in); the
+// per-instruction issue rates behind the processing element's peak.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_one(float *out, int steps, float seed) {
+    float a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = seed + (float)(threadIdx.x + 3 * i) - 100.f;
+    for (int s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            float nx[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float x = a[(i + 1) & 7];
+                if constexpr (KIND == 0) nx[i] = a[i] + x;
+                if constexpr (KIND == 1) nx[i] = __builtin_amdgcn_fmed3f(a[i], __builtin_fabsf(x), -__builtin_fabsf(x));
+                if constexpr (KIND == 2) {
+                    // written as one instruction: the compiler would otherwise
+                    // solve the xor recurrence in closed form
+                    float r;
+                    asm volatile("v_xor_b32 %0, %1, %2" : "=v"(r) : "v"(a[i]), "v"(x));
+                    nx[i] = r;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = nx[i];
+        }
+    }
+    float r = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r += a[i];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
 __global__ void __launch_bounds__(256) k_valu(float *out, int steps, float seed) {
     float a[8], b[8];
 #pragma unroll
@@ -83,14 +119,21 @@ extern "C" {
 
 // which = 0: k_valu (workgroups of 256 threads), 1: k_lds (workgroups of 1024
 // threads, 16 waves, so that two workgroups keep 8 waves per SIMD reading
-// LDS); `blocks` workgroups, `steps` loop trips, d_out at least blocks *
-// threads words.  Returns 0 or the HIP error.
+// LDS), 2..4: k_one<0..2> (256 threads, 64 instructions per trip); `blocks`
+// workgroups, `steps` loop trips, d_out at least blocks * threads words.
+// Returns 0 or the HIP error.
 int pbp_peak_launch(int which, int blocks, int steps, void *d_out, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (which == 0)
         hipLaunchKernelGGL(k_valu, dim3(blocks), dim3(256), 0, s, static_cast<float *>(d_out), steps, 0.5f);
-    else
+    else if (which == 1)
         hipLaunchKernelGGL(k_lds, dim3(blocks), dim3(1024), 0, s, static_cast<uint32_t *>(d_out), steps);
+    else if (which == 2)
+        hipLaunchKernelGGL(k_one<0>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(d_out), steps, 0.5f);
+    else if (which == 3)
+        hipLaunchKernelGGL(k_one<1>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(d_out), steps, 0.5f);
+    else
+        hipLaunchKernelGGL(k_one<2>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(d_out), steps, 0.5f);
     return (int)hipGetLastError();
 }
 
