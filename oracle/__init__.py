@@ -86,6 +86,8 @@ def lib() -> ctypes.CDLL:
         L.or_alg1_trace.argtypes = [c_i32, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, vp, vp, vp,
                                     vp, vp]
         L.or_alg1_trace.restype = ctypes.c_int
+        L.or_alg1_trace_r2.argtypes = [c_i32, c_i32, c_i32, c_u64, c_i32, vp, vp]
+        L.or_alg1_trace_r2.restype = ctypes.c_int
         L.or_sizeof_params.restype = c_i32
         L.or_sizeof_wbp_params.restype = c_i32
         if L.or_sizeof_params() != ctypes.sizeof(_Params):
@@ -114,6 +116,7 @@ class _WbpParams(ctypes.Structure):
 
 STOP_NONE, STOP_G, STOP_CRC = 0, 1, 2
 PP_NONE, PP_LASTK, PP_FULL, PP_ALG1 = -1, 0, 1, 2
+PP_ALG1_R2 = 3  # Algorithm 1 under the alternative reading R2 (blocks of the original graph)
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -428,6 +431,17 @@ def alg1_trace(N: int, P_range: int, P_level: int, D: int, N_min: int, seed: int
     if rc:
         raise ValueError(f"or_alg1_trace rc={rc}")
     return (ords, nz, add, zc, dr) if want_draws else (ords, nz, add, zc)
+
+
+def alg1_trace_r2(N: int, P_range: int, P_level: int, seed: int, n_events: int):
+    """Schedules and N_zero after each of n_events events under reading R2."""
+    n = N.bit_length() - 1
+    ords = np.zeros((n_events, N, n), np.int8)
+    nz = np.zeros(n_events, np.int32)
+    rc = lib().or_alg1_trace_r2(N, P_range, P_level, seed, n_events, _ptr(ords), _ptr(nz))
+    if rc:
+        raise ValueError(f"or_alg1_trace_r2 rc={rc}")
+    return ords, nz
 
 
 def bp_continue(L: np.ndarray, R: np.ndarray, n_iter: int, order=None, alpha: float = 1.0,

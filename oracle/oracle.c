@@ -582,6 +582,69 @@ static int alg1_event(const sched_t *sc, int32_t N, double *L, double *R, uint64
     return 0;
 }
 
+/* The alternative reading of "a subgraph of the previous factor graph is
+ * permuted" (R2): every event permutes one block of the ORIGINAL graph.  The
+ * draws are those of alg1_event (rho_range, x, the block among the N/2^m
+ * contiguous blocks of 2^m rows, then a non-identity order of the bits of
+ * stages rho_level..m, drawn from the original bits rho_level-1..m-1); the
+ * block of the previous event first returns to the original order with its
+ * inner levels reset, then the new block is re-ordered with its inner levels
+ * reset.  Every graph is the original one with one block re-ordered, so it
+ * stays a valid representation of u G_N and no draw is rejected.  N_zero is
+ * the number of (level, row) nodes reset by the event, each counted once.
+ * prev[0..2]: rho_level, m and first row of the block that is re-ordered now
+ * (prev[1] = 0: none); updated.  mark: N ints of scratch.                    */
+static int alg1_event_r2(const sched_t *sc, int32_t N, double *L, double *R, uint64_t *st,
+                         int32_t P_range, int32_t P_level, int32_t *n_zero, int32_t *prev,
+                         int32_t *mark) {
+    int n = sc->n;
+    int rr = 2 + (int)draw_below(st, (uint32_t)(P_range - 1));
+    int x = 1 + (int)draw_below(st, (uint32_t)P_level);
+    int rl = x < (n - rr + 1) ? x : (n - rr + 1);
+    int m = rl + rr - 1;
+    int32_t blk = (int32_t)draw_below(st, (uint32_t)(N >> m));
+    int8_t cand[64];
+    int ident;
+    do {
+        for (int i = 0; i < rr; i++) cand[i] = (int8_t)(rl - 1 + i);
+        for (int i = rr - 1; i >= 1; i--) {
+            uint32_t j = draw_below(st, (uint32_t)(i + 1));
+            int8_t t = cand[i]; cand[i] = cand[j]; cand[j] = t;
+        }
+        ident = 1;
+        for (int i = 0; i < rr; i++) if (cand[i] != rl - 1 + i) ident = 0;
+    } while (ident);
+    /* the nodes reset, as a bit mask of levels per row (n <= 30) */
+    for (int32_t j = 0; j < N; j++) mark[j] = 0;
+    if (prev[1] > 0) {
+        int prl = prev[0], pm = prev[1];
+        for (int32_t j = prev[2]; j < prev[2] + (1 << pm); j++) {
+            for (int s = prl; s <= pm; s++) sc->ord[(size_t)j * n + s - 1] = (int8_t)(s - 1);
+            for (int lev = prl; lev <= pm - 1; lev++) {
+                L[(size_t)lev * N + j] = 0.0;
+                R[(size_t)lev * N + j] = 0.0;
+                mark[j] |= 1 << lev;
+            }
+        }
+    }
+    int32_t r0 = blk << m;
+    for (int32_t j = r0; j < r0 + (1 << m); j++) {
+        for (int i = 0; i < rr; i++) sc->ord[(size_t)j * n + rl - 1 + i] = cand[i];
+        for (int lev = rl; lev <= m - 1; lev++) {
+            L[(size_t)lev * N + j] = 0.0;
+            R[(size_t)lev * N + j] = 0.0;
+            mark[j] |= 1 << lev;
+        }
+    }
+    int32_t nz = 0;
+    for (int32_t j = 0; j < N; j++) nz += __builtin_popcount((unsigned)mark[j]);
+    *n_zero = nz;
+    prev[0] = rl;
+    prev[1] = m;
+    prev[2] = r0;
+    return 1;
+}
+
 /* initializeIterationResetValue(N): the paper does not give it.  Reading:
  * the reset value a full permutation would get from Eq. 2 (N_zero = N(n-1)),
  * capped at half of N_it,max.                                                */
@@ -647,7 +710,8 @@ static void decode_frames(job_t *jb) {
         int32_t cur_q = 0;
         set_uniform_order(&sc, N, jb->pool);
         uint64_t st = p->seed + (uint64_t)(f + 1) * 0x9E3779B97F4A7C15ull;
-        int32_t next_reset = (p->pp_mode == 2) ? alg1_first_reset(N, n, p) : 0;
+        int32_t next_reset = (p->pp_mode == 2 || p->pp_mode == 3) ? alg1_first_reset(N, n, p) : 0;
+        int32_t prev_blk[3] = {0, 0, 0};
         int32_t it_done = p->max_iter;
         int32_t events = 0;
         int okv = 0;
@@ -675,9 +739,12 @@ static void decode_frames(job_t *jb) {
                 }
                 /* fresh channel noise on the received LLRs */
                 if (p->noise_sigma > 0.0f) inject_noise(p, jb->llr + f * N, f, it / p->T, N, L);
-            } else if (p->pp_mode == 2 && it == next_reset) {
+            } else if ((p->pp_mode == 2 || p->pp_mode == 3) && it == next_reset) {
                 int32_t nz = 0;
-                alg1_event(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, rows, mark, NULL);
+                if (p->pp_mode == 2)
+                    alg1_event(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, rows, mark, NULL);
+                else
+                    alg1_event_r2(&sc, N, L, R, &st, p->P_range, p->P_level, &nz, prev_blk, mark);
                 int32_t add = p->D > 0 ? nz / p->D : 0;
                 if (add < p->N_min) add = p->N_min;
                 next_reset = it + add;
@@ -733,12 +800,12 @@ static int decode_impl(int32_t N, int32_t K, const int32_t *info_idx, int32_t cr
     if (p->stop == 2 && crc_width == 0) return OR_EINVAL;
     if (p->pp_mode == 0 && (p->k < 2 || p->k > n)) return OR_EINVAL;
     if ((p->pp_mode == 0 || p->pp_mode == 1) && (p->T < 1 || p->Q < 1)) return OR_EINVAL;
-    if (p->pp_mode == 2 && (p->P_range < 2 || p->P_range > n || p->P_level < 1 ||
-                            p->P_level > n - 1 || p->N_min < 1))
+    if ((p->pp_mode == 2 || p->pp_mode == 3) &&
+        (p->P_range < 2 || p->P_range > n || p->P_level < 1 || p->P_level > n - 1 || p->N_min < 1))
         return OR_EINVAL;
     if (p->exact_boxplus && p->fp32) return OR_EINVAL;
     if (!(p->noise_sigma >= 0.0f) || (p->noise_sigma > 0.0f && p->pp_mode != 0 && p->pp_mode != 1 &&
-                                      p->pp_mode != 2))
+                                      p->pp_mode != 2 && p->pp_mode != 3))
         return OR_EINVAL;
     if (F == 0) return OR_OK;
     code_t c = {N, n, K, crc_width, crc_poly, info_idx, NULL};
@@ -1258,6 +1325,34 @@ int or_alg1_trace(int32_t N, int32_t P_range, int32_t P_level, int32_t D, int32_
         zeroed_out[e] = z;
     }
     free(o); free(L); free(R); free(lab); free(q);
+    return OR_OK;
+}
+
+/* The R2 reading's events on the original graph of length N (as
+ * or_alg1_trace): ord_out [n_events][N][n], nzero_out [n_events].           */
+int or_alg1_trace_r2(int32_t N, int32_t P_range, int32_t P_level, uint64_t seed, int32_t n_events,
+                     int8_t *ord_out, int32_t *nzero_out) {
+    int n = ilog2_exact(N);
+    if (n < 0 || n > 30 || P_range < 2 || P_range > n || P_level < 1 || P_level > n - 1) return OR_EINVAL;
+    size_t lvl = (size_t)(n + 1) * N;
+    int8_t *o = (int8_t *)malloc((size_t)N * n);
+    double *L = (double *)malloc(sizeof(double) * lvl);
+    double *R = (double *)malloc(sizeof(double) * lvl);
+    int32_t *mk = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    if (!o || !L || !R || !mk) { free(o); free(L); free(R); free(mk); return OR_ENOMEM; }
+    sched_t sc = {n, o};
+    for (int32_t j = 0; j < N; j++)
+        for (int s = 0; s < n; s++) o[(size_t)j * n + s] = (int8_t)s;
+    uint64_t st = seed;
+    int32_t prev[3] = {0, 0, 0};
+    for (int32_t e = 0; e < n_events; e++) {
+        for (size_t t = 0; t < lvl; t++) { L[t] = 1.0; R[t] = 1.0; }
+        int32_t nz = 0;
+        alg1_event_r2(&sc, N, L, R, &st, P_range, P_level, &nz, prev, mk);
+        memcpy(ord_out + (size_t)e * N * n, o, (size_t)N * n);
+        nzero_out[e] = nz;
+    }
+    free(o); free(L); free(R); free(mk);
     return OR_OK;
 }
 

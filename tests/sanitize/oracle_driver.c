@@ -65,8 +65,8 @@ static int run_code(int32_t N, int32_t K, int32_t cw, uint32_t poly, int64_t F) 
     base.pp_mode = -1;
     base.seed = 11;
     base.fp32 = 1;
-    for (int mode = -1; mode <= 2; mode++) {
-        if (mode == 2 && n < 3) continue;
+    for (int mode = -1; mode <= 3; mode++) {
+        if (mode >= 2 && n < 3) continue;
         or_params p = base;
         p.pp_mode = mode;
         p.k = n >= 3 ? 3 : n;
@@ -127,6 +127,7 @@ static int run_code(int32_t N, int32_t K, int32_t cw, uint32_t poly, int64_t F) 
         int32_t a[E], b[E], c[E];
         int32_t *dr = (int32_t *)malloc(sizeof(int32_t) * E * (4 + n));
         CHECK(or_alg1_trace(N, n, n - 1, 4, 2, 3, E, ords, a, b, c, dr));
+        CHECK(or_alg1_trace_r2(N, n, n - 1, 5, E, ords, a));
         free(ords); free(dr);
     }
     for (int j = 0; j < 8; j++) (void)or_noise_gauss(7, j, j + 1, j * 3);

@@ -189,3 +189,55 @@ def test_fp32_fp64_fer_agree(orc):
     lo = beta.ppf(0.025, e, F - e + 1) if e else 0.0
     hi = beta.ppf(0.975, e + 1, F - e)
     assert lo <= errs[True] / F <= hi
+
+
+def _changed_rows(o, n):
+    ident = np.arange(n, dtype=np.int8)
+    return np.nonzero((o != ident).any(1))[0]
+
+
+@pytest.mark.parametrize("N,pr,pl", [(64, 6, 5), (256, 8, 7), (1024, 10, 9), (1024, 2, 6)])
+def test_alg1_r2_events_keep_graph_valid(orc, N, pr, pl):
+    # reading R2 of Algorithm 1: each event restores the previous block and
+    # permutes one aligned block of the ORIGINAL graph, so after every event the
+    # schedule is the identity outside one block of 2^m rows
+    n = N.bit_length() - 1
+    ords, nz = orc.alg1_trace_r2(N, pr, pl, seed=N + pr, n_events=30)
+    rng = np.random.default_rng(2)
+    prev_sz = 0
+    for e in range(30):
+        u = rng.integers(0, 2, N).astype(np.uint8)
+        assert np.array_equal(orc.graph_encode(ords[e], u), orc.polar_transform(u))
+        rows = _changed_rows(ords[e], n)
+        size = len(rows)
+        m = size.bit_length() - 1
+        assert size == 1 << m and m >= 2
+        assert rows[0] % size == 0 and np.array_equal(rows, rows[0] + np.arange(size))
+        # every row of the block carries the same stage order
+        assert (ords[e][rows] == ords[e][rows[0]]).all()
+        # nodes of levels rl..m-1 of the block: 2^m (rho_range - 1) of them,
+        # plus those of the previous block that are not in this one
+        assert nz[e] >= size
+        if e == 0:
+            assert nz[e] % size == 0 and 1 <= nz[e] // size <= pr - 1
+        else:
+            assert nz[e] <= prev_sz * (pr - 1) + size * (pr - 1)
+        prev_sz = size
+
+
+def test_alg1_r2_decode_runs_and_matches_plain_bp_before_first_event(orc):
+    code, msg, llr = _frames(orc, 256, 144, 16, 0x1021, 16, 2.5, 6)
+    base = dict(max_iter=200, stop=orc.STOP_CRC, it_min=3, P_range=8, P_level=7, D=20, N_min=5,
+                seed=2)
+    r2 = orc.decode(code, llr, orc.DecodeParams(pp_mode=orc.PP_ALG1_R2, **base))
+    assert np.all((r2.iters >= 3) & (r2.iters <= 200))
+    assert (r2.msg_hat != msg).any(1).mean() < 0.5
+    # the first event comes after alg1_first_reset iterations: frames that stop
+    # earlier are decoded exactly as plain BP decodes them
+    plain = orc.decode(code, llr, orc.DecodeParams(pp_mode=orc.PP_NONE, max_iter=200,
+                                                   stop=orc.STOP_CRC, it_min=3))
+    first = min(max(256 * 7 // 20, 5), 100)
+    early = plain.iters < first
+    assert early.any()
+    assert np.array_equal(r2.iters[early], plain.iters[early])
+    assert np.array_equal(r2.msg_hat[early], plain.msg_hat[early])
