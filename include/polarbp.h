@@ -48,6 +48,8 @@ extern "C" {
                            permutations (Sec. II-D); only L_1 and R_{n+1} survive     */
 #define PC_PP_ALG1 2    /* Algorithm 1: a random subgraph re-ordered per event, the
                            events spaced by Eq. 2 (see pc_pp_params)                  */
+#define PC_PP_ALG1_ORIG 3 /* Algorithm 1 with each event's subgraph taken from the
+                           original graph (see pc_pp_params)                          */
 
 /* Opaque polar code: frozen set, CRC, and device copies of the per-row
  * tables the decoder reads.  Immutable after construction; may be shared by
@@ -121,7 +123,16 @@ typedef struct {
  * 2 <= P_range <= n, 1 <= P_level <= n-1, N_min >= 1.  On the GPU: N = 16 ..
  * 1024, codes with a CRC and PC_STOP_CRC or PC_STOP_NONE; one frame per
  * workgroup, one row per thread (messages in registers, the levels partners
- * read in LDS), so no launch configuration.                                */
+ * read in LDS), so no launch configuration.
+ * PC_PP_ALG1_ORIG reads Sec. III's subgraph as one of the N/2^m aligned blocks
+ * of the ORIGINAL graph: the draws are rho_range, rho_level (as above), the
+ * block index in [0, N/2^m), then the order of bits rho_level-1..m-1 (the same
+ * non-identity shuffle), with no redraw.  Before permuting, the block of the
+ * previous event returns to the original order, so the graph differs from
+ * the original in at most one block; the R messages on the inner levels
+ * rho_level..m-1 of both blocks are reset, and N_zero of Eq. 2 counts the
+ * union of those nodes.  Parameters, limits, spacing and noise as for
+ * PC_PP_ALG1; on the GPU one processing element per thread.                */
 
 /* Launch configuration picked by the autotuner; NULL selects the library's
  * table.  rho: log2 rows held per thread per level (2 or 3); slots: frames

@@ -117,6 +117,7 @@ class _WbpParams(ctypes.Structure):
 STOP_NONE, STOP_G, STOP_CRC = 0, 1, 2
 PP_NONE, PP_LASTK, PP_FULL, PP_ALG1 = -1, 0, 1, 2
 PP_ALG1_R2 = 3  # Algorithm 1 under the alternative reading R2 (blocks of the original graph)
+PP_ALG1_ORIG = PP_ALG1_R2  # the library's name for the same mode
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -10,7 +10,7 @@ functions raises.
 from __future__ import annotations
 
 from ._lib import (PolarError, PC_OK, PC_EINVAL, PC_ENOTSUP, PC_EHIP, PC_ENOMEM,
-                   STOP_NONE, STOP_G, STOP_CRC, PP_NONE, PP_LASTK, PP_FULL, PP_ALG1,
+                   STOP_NONE, STOP_G, STOP_CRC, PP_NONE, PP_LASTK, PP_FULL, PP_ALG1, PP_ALG1_ORIG,
                    ERR_CORRECT, ERR_FALSE_CONVERGED, ERR_OSCILLATION, ERR_UNCONVERGED,
                    CHECK_MINSUM, CHECK_EXACT, lib, library_path)
 from .api import (Code, BPParams, PPParams, LaunchCfg, trellis_pool, encode, info_bits, bp_decode,
@@ -19,7 +19,7 @@ from .api import (Code, BPParams, PPParams, LaunchCfg, trellis_pool, encode, inf
 
 __all__ = [
     "PolarError", "PC_OK", "PC_EINVAL", "PC_ENOTSUP", "PC_EHIP", "PC_ENOMEM",
-    "STOP_NONE", "STOP_G", "STOP_CRC", "PP_NONE", "PP_LASTK", "PP_FULL", "PP_ALG1",
+    "STOP_NONE", "STOP_G", "STOP_CRC", "PP_NONE", "PP_LASTK", "PP_FULL", "PP_ALG1", "PP_ALG1_ORIG",
     "lib", "library_path", "Code", "BPParams", "PPParams", "LaunchCfg", "trellis_pool",
     "encode", "info_bits", "bp_decode", "pp_mt_bp_decode", "decode_batched", "batched_workspace_bytes",
     "wbp_workspace_bytes", "wbp_forward", "wbp_backward", "pp_mt_bp_decode_trace",

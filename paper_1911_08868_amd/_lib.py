@@ -10,6 +10,7 @@ _LIB_PATH = os.path.join(_HERE, "libpolarbp.so")
 PC_OK, PC_EINVAL, PC_ENOTSUP, PC_EHIP, PC_ENOMEM = 0, -1, -2, -3, -4
 STOP_NONE, STOP_G, STOP_CRC = 0, 1, 2
 PP_NONE, PP_LASTK, PP_FULL, PP_ALG1 = -1, 0, 1, 2
+PP_ALG1_ORIG = 3  # Algorithm 1 with subgraphs of the original graph
 
 # symbols declared in include/polarbp.h
 EXPORTS = [

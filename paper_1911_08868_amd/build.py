@@ -46,7 +46,7 @@ def _units():
                       [f"-DPBP_NLOG={n}", "-DPBP_VARIANT=3"]))
     for n in range(4, 13):
         units.append((os.path.join(CSRC, "wbp_inst.hip"), f"wbp_n{n:02d}.o", [f"-DPBP_NLOG={n}"]))
-    for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip", "alg1.hip", "diag.hip"):
+    for src in ("host.cpp", "dispatch.cpp", "encode.hip", "wbp.hip", "batched.hip", "alg1.hip", "alg1_orig.hip", "diag.hip"):
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         units.append((os.path.join(CSRC, src), os.path.splitext(src)[0] + ".o", lang))
     return units

@@ -43,36 +43,9 @@
 // ranked by their smallest row.
 #include <climits>
 
-#include "bp_core.h"
-#include "internal.h"
+#include "alg1_common.h"
 
 namespace pbp {
-
-struct Alg1Args {
-    const float *llr;
-    int64_t F;
-    uint8_t *msg;
-    int32_t *iters;
-    uint8_t *ok;
-    float *soft;
-    const uint32_t *syn;
-    const int32_t *meta;
-    uint32_t *counter;
-    int32_t K_msg, max_iter, it_min, stop;
-    float alpha;
-    int32_t P_range, P_level, D, N_min, first_reset;
-    uint64_t seed;
-    uint64_t *hist;  // [F][H] decision hashes, or NULL
-    int32_t H;
-    float noise_sigma;  // > 0: channel level y + sigma g(frame, e, j) after event e
-    uint64_t noise_seed;
-};
-
-// uniform integer in [0, m): the high 32 bits of the next output, scaled by m
-__device__ __forceinline__ uint32_t draw_below(uint64_t &s, uint32_t m) {
-    const uint64_t hi = splitmix64_next(s) >> 32;
-    return (uint32_t)((hi * (uint64_t)m) >> 32);
-}
 
 template <int NLOG>
 struct Alg1Lds {
@@ -86,16 +59,6 @@ struct Alg1Lds {
     static constexpr size_t bytes = msg_floats * 4 + 352 * 4 + (size_t)N * 4;
     static constexpr int threads = N >= 64 ? N : 64;  // one row per thread
 };
-
-// Check function of the processing elements: CN 0 min-sum, 1 scaled min-sum
-// (the clamp form: equal to the FP32 oracle's values, a zero possibly with
-// the other sign; x is the bound, an L operand as in the fixed-schedule
-// kernels), 2 the exact boxplus (FP32 on the hardware exp2/log2).
-template <int CN>
-__device__ __forceinline__ float alg1_check(float x, float y, float alpha) {
-    if constexpr (CN == 2) return cnode_exact(x, y);
-    else return cnode_clamp<CN>(x, y, alpha);
-}
 
 // 8 waves per SIMD: two 1024-row frames per CU (the LDS of one is 77 KiB)
 template <int NLOG, int CN>
@@ -248,14 +211,7 @@ __global__ void __launch_bounds__(Alg1Lds<NLOG>::threads, 8) k_alg1(Alg1Args a) 
             synl[j] = a.syn[j];  // read back by this thread only
         }
         uint64_t st = a.seed + (uint64_t)(frame + 1) * 0x9E3779B97F4A7C15ull;
-        int next_reset;
-        if (a.first_reset > 0) {
-            next_reset = a.first_reset;
-        } else {
-            const int full = a.D > 0 ? (N * (n - 1)) / a.D : 0;
-            const int v = full > a.N_min ? full : a.N_min;
-            next_reset = v < a.max_iter / 2 ? v : a.max_iter / 2;
-        }
+        int next_reset = alg1_first_event(a, N, n);
         int ev = 0;  // events so far with noise injected (Sec. V reading)
         update_cross(row);
         load_pairs(row, j, src, frame, ev);
@@ -501,6 +457,7 @@ static int run_alg1_n(const Alg1Args &a, int cn, hipStream_t s) {
 int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_params &bp,
                 const pc_pp_params &pp, uint8_t *d_msg, int32_t *d_iters, uint8_t *d_ok, float *d_soft,
                 uint64_t *d_hist, int32_t H, hipStream_t s) {
+    const bool orig = pp.mode == PC_PP_ALG1_ORIG;
     const int n = c->n;
     if (n < 4 || n > 10) return fail(PC_ENOTSUP, "Algorithm 1 on the GPU is built for N = 16 .. 1024");
     if (bp.stop == PC_STOP_G || (bp.stop == PC_STOP_NONE && c->crc_width == 0))
@@ -538,6 +495,7 @@ int launch_alg1(const pc_code *c, const float *d_llr, int64_t F, const pc_bp_par
     a.noise_sigma = pp.noise_sigma;
     a.noise_seed = pp.seed;
     const int cn = bp.check == PC_CHECK_EXACT ? 2 : bp.alpha != 1.0f ? 1 : 0;
+    if (orig) return run_alg1_orig(a, n, cn, s);
     switch (n) {
         case 4: return run_alg1_n<4>(a, cn, s);
         case 5: return run_alg1_n<5>(a, cn, s);

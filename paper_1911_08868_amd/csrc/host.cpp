@@ -353,11 +353,11 @@ static int decode_common(const pc_code *code, const float *d_llr, int64_t F, con
     const float sigma = pp ? pp->noise_sigma : 0.f;
     if (!(sigma >= 0.f) || !std::isfinite(sigma)) return fail(PC_EINVAL, "noise_sigma must be finite and >= 0");
     if (sigma > 0.f) {
-        if (mode != PC_PP_LASTK && mode != PC_PP_FULL && mode != PC_PP_ALG1)
-            return fail(PC_EINVAL, "noise is injected at the trellis events (LASTK, FULL, ALG1)");
+        if (mode != PC_PP_LASTK && mode != PC_PP_FULL && mode != PC_PP_ALG1 && mode != PC_PP_ALG1_ORIG)
+            return fail(PC_EINVAL, "noise is injected at the trellis events (LASTK, FULL, ALG1, ALG1_ORIG)");
         if (exact || d_hist) return fail(PC_ENOTSUP, "noise injection is built for min-sum without history");
     }
-    if (mode == PC_PP_ALG1) {
+    if (mode == PC_PP_ALG1 || mode == PC_PP_ALG1_ORIG) {
         if (cfg && (cfg->rho || cfg->slots || cfg->grid))
             return fail(PC_EINVAL, "Algorithm 1 takes no launch shape (one frame per workgroup)");
         return launch_alg1(code, d_llr, F, *bp, *pp, d_msg, d_iters, d_ok, d_soft, d_hist, H,

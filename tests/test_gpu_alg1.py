@@ -1,8 +1,10 @@
 """GPU parity of Algorithm 1 (random-subgraph partial permutations, Eq. 2
-reset spacing) against the oracle: decided bits, iteration counts, verdicts
-bit-exact and the u-side L messages equal as FP32 values and bit-identical
-wherever nonzero (the clamp form of min-sum may give a zero the other sign)
-on the paper's Table I parameter sets and edge settings."""
+reset spacing) against the oracle, under both readings of its subgraph (a
+component of the current graph, PP_ALG1; an aligned block of the original
+graph, PP_ALG1_ORIG): decided bits, iteration counts, verdicts bit-exact and
+the u-side L messages equal as FP32 values and bit-identical wherever nonzero
+(the clamp form of min-sum may give a zero the other sign) on the paper's
+Table I parameter sets and edge settings."""
 import json
 import os
 
@@ -15,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "published_constants.json")))
 TABLE1 = GOLD["table1_pp_bp_parameters"]
+MODES = pytest.mark.parametrize("mode", [2, 3], ids=["current", "orig"])  # PP_ALG1, PP_ALG1_ORIG
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +29,7 @@ def pbp():
 
 
 def _run(orc, pbp, N, K, cw, poly, F, snr, seed, max_iter, stop, it_min, P_range, P_level, D, N_min,
-         first_reset=0, alpha=1.0, pp_seed=3, dsnr=2.5):
+         first_reset=0, alpha=1.0, pp_seed=3, dsnr=2.5, mode=2):
     import torch
     oc = orc.construct(N, K, dsnr, cw, poly)
     msg = synth.message_bits(seed, F, oc.K_msg)
@@ -34,12 +37,12 @@ def _run(orc, pbp, N, K, cw, poly, F, snr, seed, max_iter, stop, it_min, P_range
     llr = synth.awgn_llr(x, snr, oc.K_msg, seed=seed)
     code = pbp.Code(N, K, cw, poly, dsnr)
     bp = pbp.BPParams(max_iter=max_iter, alpha=alpha, stop=stop, it_min=it_min)
-    pp = pbp.PPParams(mode=pbp.PP_ALG1, P_range=P_range, P_level=P_level, D=D, N_min=N_min,
+    pp = pbp.PPParams(mode=mode, P_range=P_range, P_level=P_level, D=D, N_min=N_min,
                       first_reset=first_reset, seed=pp_seed)
     m, it, ok, soft = pbp.pp_mt_bp_decode(code, torch.from_numpy(llr).cuda(), bp, pp, soft=True)
     torch.cuda.synchronize()
     ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=max_iter, alpha=alpha, stop=stop, it_min=it_min,
-                                               pp_mode=orc.PP_ALG1, P_range=P_range, P_level=P_level,
+                                               pp_mode=mode, P_range=P_range, P_level=P_level,
                                                D=D, N_min=N_min, first_reset=first_reset, seed=pp_seed,
                                                fp32=True), soft=True, threads=8)
     return (m.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy(), soft.cpu().numpy()), ref, msg
@@ -56,32 +59,36 @@ def _assert_parity(got, ref, tag):
 
 
 @pytest.mark.parametrize("cw,poly", [(16, 0x1021), (24, 0x1864CFB)])
-def test_table1_n1024_200_iterations(orc, pbp, cw, poly):
+@MODES
+def test_table1_n1024_200_iterations(orc, pbp, mode, cw, poly):
     t = TABLE1["N1024_Nitmax200"]
     got, ref, msg = _run(orc, pbp, 1024, 512, cw, poly, 48, 1.75, 21, 200, orc.STOP_CRC, 3,
-                         t["P_range"], t["P_level"], t["D"], t["N_min"])
+                         t["P_range"], t["P_level"], t["D"], t["N_min"], mode=mode)
     _assert_parity(got, ref, f"Table I N=1024 200 it, CRC-{cw}")
     assert ref.iters.max() > 40  # frames that went through many events
 
 
-def test_table1_n1024_long_budget_parameters(orc, pbp):
+@MODES
+def test_table1_n1024_long_budget_parameters(orc, pbp, mode):
     # the 2e4-iteration parameter set (ranges up to the whole graph) on a
     # shorter budget
     t = TABLE1["N1024_Nitmax20000"]
     got, ref, _ = _run(orc, pbp, 1024, 512, 24, 0x1864CFB, 24, 1.5, 22, 300, orc.STOP_CRC, 3,
-                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+                       t["P_range"], t["P_level"], t["D"], t["N_min"], mode=mode)
     _assert_parity(got, ref, "Table I N=1024 2e4 set")
 
 
-def test_table1_n512_rate_065(orc, pbp):
+@MODES
+def test_table1_n512_rate_065(orc, pbp, mode):
     t = TABLE1["N512_Nitmax20000"]
     K = int(round(0.65 * 512))
     got, ref, _ = _run(orc, pbp, 512, K, 24, 0x1864CFB, 40, 2.0, 23, 300, orc.STOP_CRC, 3,
-                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+                       t["P_range"], t["P_level"], t["D"], t["N_min"], mode=mode)
     _assert_parity(got, ref, "Table I N=512 R=0.65")
 
 
-def test_table1_large_workload_sampled(orc, pbp):
+@MODES
+def test_table1_large_workload_sampled(orc, pbp, mode):
     # 16384 frames of the 1024-bit code in one launch (two frames per CU, many
     # refills from the queue): the first 1024 frames' decided bits and
     # iteration counts bit-exact against the oracle, and the verdicts of a
@@ -95,11 +102,11 @@ def test_table1_large_workload_sampled(orc, pbp):
     llr = synth.awgn_llr(x, 2.0, oc.K_msg, seed=91)
     code = pbp.Code(1024, 512, 24, 0x1864CFB, 2.5)
     bp = pbp.BPParams(max_iter=200, stop=orc.STOP_CRC, it_min=3)
-    pp = pbp.PPParams(mode=pbp.PP_ALG1, P_range=t["P_range"], P_level=t["P_level"], D=t["D"],
+    pp = pbp.PPParams(mode=mode, P_range=t["P_range"], P_level=t["P_level"], D=t["D"],
                       N_min=t["N_min"], seed=2)
     m, it, ok = [a.cpu().numpy() for a in pbp.pp_mt_bp_decode(code, torch.from_numpy(llr).cuda(), bp, pp)]
     ref = orc.decode(oc, llr[:P], orc.DecodeParams(max_iter=200, stop=orc.STOP_CRC, it_min=3,
-                                                   pp_mode=orc.PP_ALG1, P_range=t["P_range"],
+                                                   pp_mode=mode, P_range=t["P_range"],
                                                    P_level=t["P_level"], D=t["D"], N_min=t["N_min"],
                                                    seed=2, fp32=True), threads=8)
     rng = np.random.default_rng(5)
@@ -111,14 +118,16 @@ def test_table1_large_workload_sampled(orc, pbp):
 
 @pytest.mark.parametrize("set_name,N,K", [("N1024_Nitmax20000", 1024, 512),
                                           ("N512_Nitmax20000", 512, 333)])
-def test_table1_long_budget_many_events(orc, pbp, set_name, N, K):
+@MODES
+def test_table1_long_budget_many_events(orc, pbp, mode, set_name, N, K):
     # frames that do not converge within 3000 iterations go through well over
-    # a hundred events each, where valid blocks get rare and most events redraw
-    # several times: the component labels, the block test and the draws after
-    # many permutations
+    # a hundred events each; under the current-graph reading valid blocks get
+    # rare and most events redraw several times (the component labels, the
+    # block test and the draws after many permutations), under the
+    # original-graph reading blocks of every size replace each other
     t = TABLE1[set_name]
     got, ref, _ = _run(orc, pbp, N, K, 24, 0x1864CFB, 8, 0.5, 24 + N, 3000, orc.STOP_CRC, 3,
-                       t["P_range"], t["P_level"], t["D"], t["N_min"])
+                       t["P_range"], t["P_level"], t["D"], t["N_min"], mode=mode)
     _assert_parity(got, ref, f"Table I {set_name}, 3000 iterations")
     assert (ref.iters == 3000).sum() >= 4
 
@@ -129,14 +138,18 @@ def test_table1_long_budget_many_events(orc, pbp, set_name, N, K):
     (256, 144, 8, 7, 20, 5, 0, 1.0),
     (16, 12, 4, 3, 1, 1, 2, 1.0),        # tiny code, every component is small
 ])
-def test_alg1_edge_settings(orc, pbp, N, K, P_range, P_level, D, N_min, first_reset, alpha):
+@MODES
+def test_alg1_edge_settings(orc, pbp, mode, N, K, P_range, P_level, D, N_min, first_reset, alpha):
     got, ref, _ = _run(orc, pbp, N, K, 8 if N < 64 else 16, 0x07 if N < 64 else 0x1021, 150, 1.0,
-                       N + P_range, 120, orc.STOP_CRC, 3, P_range, P_level, D, N_min, first_reset, alpha)
+                       N + P_range, 120, orc.STOP_CRC, 3, P_range, P_level, D, N_min, first_reset, alpha,
+                       mode=mode)
     _assert_parity(got, ref, f"N={N} P_range={P_range} P_level={P_level} D={D}")
 
 
-def test_alg1_no_early_stop(orc, pbp):
-    got, ref, _ = _run(orc, pbp, 256, 128, 16, 0x1021, 40, 2.5, 5, 37, orc.STOP_NONE, 1, 5, 4, 10, 3)
+@MODES
+def test_alg1_no_early_stop(orc, pbp, mode):
+    got, ref, _ = _run(orc, pbp, 256, 128, 16, 0x1021, 40, 2.5, 5, 37, orc.STOP_NONE, 1, 5, 4, 10, 3,
+                       mode=mode)
     _assert_parity(got, ref, "no stop")
     assert np.all(got[1] == 37)
 
