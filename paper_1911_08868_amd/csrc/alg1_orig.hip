@@ -198,9 +198,16 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
     auto crosses = [&](uint32_t ss) -> bool {
         return (int)((ss & 0xFFFFu) >> 7) != wave || (int)(ss >> 23) != wave;
     };
-    // the exchange slots and masks for the current block; the barrier needs
-    // are published as wave flags in misc[32 + w] (read after the caller's
-    // next barrier)
+    // The threads whose rows change coordinates at A: those with an element in
+    // the block (the two stages share the thread map, and the butterfly there
+    // pairs elements of one block); at B: the block's elements and their
+    // butterfly partners, the elements of the sibling block, whose pairs at
+    // stage m+1 hold one row of each.  Every other thread keeps its butterfly.
+    auto in_a = [&](int e) -> bool { return (e >> (m - 1)) == blk; };
+    auto in_b = [&](int e) -> bool { return (e >> m) == (blk >> 1); };
+    // the exchange slots and masks for the current block (the C slots again
+    // only if redo_c); the barrier needs are published as wave flags in
+    // misc[32 + w] (read after the caller's next barrier)
     auto set_exchanges = [&](bool redo_c) {
         lmask = rmask = 0u;
         bool ca = false, cb = false;
@@ -217,11 +224,11 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
         if (pe) {
             if constexpr (W > 0)
                 if (redo_c) cS = slots(6);
-            if (hasA) {
+            if (hasA && in_a(elem(rl - 1))) {
                 aS = slots(rl - 1);
                 ca = crosses(aS);
             }
-            if (hasB) {
+            if (hasB && in_b(elem(m))) {
                 bS = slots(m);
                 cb = crosses(bS);
             }
@@ -237,15 +244,17 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
     // one exchange (backwards: the R direction): with a workgroup barrier
     // (alternating buffers) or within the waves (their own slots of the third
     // buffer)
-    auto exchange = [&](float &v0, float &v1, uint32_t ss, bool barrier, bool back) {
+    // (u0, u1): the pair the thread stores; only threads with `part` take part
+    auto exchange = [&](float &v0, float &v1, float u0, float u1, uint32_t ss, bool barrier, bool back,
+                        bool part) {
         float *const xb = smem + (size_t)(barrier ? xsel : 2) * N;
         if (barrier) xsel ^= 1;
-        if (pe) {
+        if (part) {
             if (back) {
-                xb[ss & 0xFFFFu] = v0;
-                xb[ss >> 16] = v1;
+                xb[ss & 0xFFFFu] = u0;
+                xb[ss >> 16] = u1;
             } else {
-                *reinterpret_cast<float2 *>(xb + own) = own_swap ? make_float2(v1, v0) : make_float2(v0, v1);
+                *reinterpret_cast<float2 *>(xb + own) = own_swap ? make_float2(u1, u0) : make_float2(u0, u1);
             }
         }
         if (barrier) {
@@ -255,7 +264,7 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (pe) {
+        if (part) {
             if (back) {
                 const float2 v = *reinterpret_cast<const float2 *>(xb + own);
                 v0 = own_swap ? v.y : v.x;
@@ -352,19 +361,21 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
                 float lb = alg1_check<CN>(a0, r0, alpha) + a1;
                 if constexpr (s < n) {
                     if constexpr (W > 0 && s == 6) {
-                        exchange(lt, lb, cS, true, false);
+                        exchange(lt, lb, lt, lb, cS, true, false, pe);
                     } else {
-                        // the butterfly in place; at a block boundary it is
-                        // undone (it is an involution) and the pair moves
-                        // through LDS instead
+                        // the butterfly in place; at a block boundary the
+                        // threads whose rows change coordinates move the pair
+                        // they had (the butterfly undone on copies: it is an
+                        // involution) through LDS instead
                         constexpr int K = W == 0 ? s - 1 : s >= 7 ? s - 4 : s;
                         bfly_wave<K>(lt, lb, lane);
                         if (__builtin_expect((lmask >> s) & 1u, 0)) {
-                            bfly_wave<K>(lt, lb, lane);
+                            float u0 = lt, u1 = lb;
+                            bfly_wave<K>(u0, u1, lane);
                             if (s == rl - 1)
-                                exchange(lt, lb, aS, abar & 1u, false);
+                                exchange(lt, lb, u0, u1, aS, abar & 1u, false, pe && in_a(elem(s)));
                             else
-                                exchange(lt, lb, bS, abar & 2u, false);
+                                exchange(lt, lb, u0, u1, bS, abar & 2u, false, pe && in_b(elem(s)));
                         }
                     }
                     Li[s + 1][0] = lt;
@@ -420,17 +431,18 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
                 float rt = alg1_check<CN>(q1 + p1, p0, alpha);
                 float rb = alg1_check<CN>(q0, p0, alpha) + p1;
                 if constexpr (W > 0 && s == 7) {
-                    exchange(rt, rb, cS, true, true);
+                    exchange(rt, rb, rt, rb, cS, true, true, pe);
                     if (gather(frame, it) && can_stop) done = true;
                 } else {
                     constexpr int K = W == 0 ? s - 2 : s >= 8 ? s - 5 : s - 1;
                     bfly_wave<K>(rt, rb, lane);
                     if (__builtin_expect((rmask >> s) & 1u, 0)) {
-                        bfly_wave<K>(rt, rb, lane);
+                        float u0 = rt, u1 = rb;
+                        bfly_wave<K>(u0, u1, lane);
                         if (s == rl)
-                            exchange(rt, rb, aS, abar & 1u, true);
+                            exchange(rt, rb, u0, u1, aS, abar & 1u, true, pe && in_a(elem(s)));
                         else
-                            exchange(rt, rb, bS, abar & 2u, true);
+                            exchange(rt, rb, u0, u1, bS, abar & 2u, true, pe && in_b(elem(s)));
                     }
                 }
                 Ri[s - 1][0] = rt;
