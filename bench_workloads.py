@@ -272,15 +272,27 @@ def weighted_bp_large(torch, pbp, F_train=1024, F_dec=8192, T=20, steps=2, warmu
                        "points": fer}}
 
 
+def _alu_roof(ops, ms):
+    achieved = ops / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK / 1e12, 2), "unit": "TOP/s",
+            "frac": round(achieved * 1e12 / ALU_PEAK, 4)}
+
+
 def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
     """Algorithm 1 with random subgraphs (Table I, N_it,max = 200: P_range 2,
-    P_level 6, D 8, N_min 4) at N=1024, R=1/2 (K=512 with CRC-24), beside
-    the fixed last-4 schedule on the same frames."""
+    P_level 6, D 8, N_min 4) at N=1024, R=1/2 (K=512 with CRC-24), under both
+    readings of its subgraph (a component of the current graph; a block of the
+    original graph), beside the fixed last-4 schedule on the same frames, and
+    both with the exact boxplus.  Roofline entries count the processing
+    elements' 6 lane-ops: 3 N (2n - 1) per frame-iteration."""
     import synth
     code = pbp.Code(1024, 512, 24, 0x1864CFB, 2.5)
+    ops_fi = 3 * 1024 * (2 * 10 - 1)
     bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
     bp_exact = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3, check=pbp.CHECK_EXACT)
-    alg1 = pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)
+    t = dict(P_range=2, P_level=6, D=8, N_min=4, seed=1)
+    alg1 = pbp.PPParams(mode=pbp.PP_ALG1, **t)
+    orig = pbp.PPParams(mode=pbp.PP_ALG1_ORIG, **t)
     lastk = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
     points = []
     for snr in snrs:
@@ -291,7 +303,8 @@ def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
         llr = synth.awgn_llr_torch(x, torch.full((F,), snr, device="cuda", dtype=torch.float64),
                                    code.K_msg, gen)
         row = {"ebn0_db": snr}
-        for name, pp, bpx in (("alg1", alg1, bp), ("lastk4", lastk, bp), ("alg1_exact", alg1, bp_exact)):
+        for name, pp, bpx in (("alg1", alg1, bp), ("alg1_orig", orig, bp), ("lastk4", lastk, bp),
+                              ("alg1_exact", alg1, bp_exact), ("alg1_orig_exact", orig, bp_exact)):
             out = pbp.pp_mt_bp_decode(code, llr, bpx, pp)
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -300,23 +313,29 @@ def alg1_table1(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0)):
             b.record()
             torch.cuda.synchronize()
             ms = a.elapsed_time(b)
+            fi = out[1].double().sum().item()
             row[name] = {"gbit_s": round(F * code.K_msg / (ms / 1e3) / 1e9, 3), "ms": round(ms, 2),
-                         "avg_iters": round(out[1].double().mean().item(), 3),
+                         "avg_iters": round(fi / F, 3), "frame_it_s": round(fi / (ms / 1e3)),
                          "fer": (out[0] != m).any(1).double().mean().item()}
+            if name != "lastk4" and not name.endswith("exact"):
+                row[name]["roofline"] = _alu_roof(ops_fi * fi, ms)
         points.append(row)
-        _log(f"Algorithm 1 at {snr} dB: {row['alg1']['ms']} ms vs last-4 {row['lastk4']['ms']} ms; "
-             f"with the exact boxplus {row['alg1_exact']['ms']} ms, fer {row['alg1_exact']['fer']:.4g} "
-             f"(min-sum {row['alg1']['fer']:.4g})")
-    return {"workload": f"Algorithm 1 (Table I, 200-iteration set: P_range 2, P_level 6, D 8, N_min 4) vs "
-                        f"fixed last-4 schedule, and Algorithm 1 with the exact boxplus, N=1024 K=512 incl. "
-                        f"CRC-24, {F} frames per Eb/N0 point, max 200 iterations, CRC stop", "points": points}
+        _log(f"Algorithm 1 at {snr} dB: current-graph {row['alg1']['ms']} ms "
+             f"({row['alg1']['frame_it_s']:.3g} frame-it/s), original-graph {row['alg1_orig']['ms']} ms "
+             f"({row['alg1_orig']['frame_it_s']:.3g}), last-4 {row['lastk4']['ms']} ms; fer "
+             f"{row['alg1']['fer']:.4g} / {row['alg1_orig']['fer']:.4g} / {row['lastk4']['fer']:.4g}")
+    return {"workload": f"Algorithm 1 (Table I, 200-iteration set: P_range 2, P_level 6, D 8, N_min 4), subgraph "
+                        f"of the current graph (alg1) and of the original graph (alg1_orig), vs fixed last-4 "
+                        f"schedule, and both with the exact boxplus, N=1024 K=512 incl. CRC-24, {F} frames per "
+                        f"Eb/N0 point, max 200 iterations, CRC stop", "points": points}
 
 
 def alg1_long(torch, pbp, F=8192, snrs=(2.0, 2.5, 3.0)):
     """Algorithm 1 with Table I's 2e4-iteration sets at their full budget:
     N=1024 R=1/2 (P_range 10, P_level 9, D 100, N_min 15) and N=512 R=0.65
-    (K=333 with CRC-24; P_range 9, P_level 8, D 50, N_min 15), beside plain
-    BP with the same budget on the same frames."""
+    (K=333 with CRC-24; P_range 9, P_level 8, D 50, N_min 15), under both
+    readings of its subgraph, beside plain BP with the same budget on the same
+    frames."""
     import synth
     sets = (("N1024_R0.5", 1024, 512, dict(P_range=10, P_level=9, D=100, N_min=15)),
             ("N512_R0.65", 512, 333, dict(P_range=9, P_level=8, D=50, N_min=15)))
@@ -325,9 +344,11 @@ def alg1_long(torch, pbp, F=8192, snrs=(2.0, 2.5, 3.0)):
     for name, N, K, t in sets:
         code = pbp.Code(N, K, 24, 0x1864CFB, 2.5)
         alg1 = pbp.PPParams(mode=pbp.PP_ALG1, seed=1, **t)
+        orig = pbp.PPParams(mode=pbp.PP_ALG1_ORIG, seed=1, **t)
         # first launch of this length's kernels, outside the timed calls
         warm = torch.zeros((64, N), dtype=torch.float32, device="cuda")
         pbp.pp_mt_bp_decode(code, warm, pbp.BPParams(max_iter=5, stop=pbp.STOP_CRC), alg1)
+        pbp.pp_mt_bp_decode(code, warm, pbp.BPParams(max_iter=5, stop=pbp.STOP_CRC), orig)
         pbp.bp_decode(code, warm, pbp.BPParams(max_iter=5, stop=pbp.STOP_CRC))
         points = []
         for snr in snrs:
@@ -338,6 +359,7 @@ def alg1_long(torch, pbp, F=8192, snrs=(2.0, 2.5, 3.0)):
                                                                        dtype=torch.float64), code.K_msg, gen)
             row = {"ebn0_db": snr}
             for dec, run in (("alg1", lambda: pbp.pp_mt_bp_decode(code, llr, bp, alg1)),
+                             ("alg1_orig", lambda: pbp.pp_mt_bp_decode(code, llr, bp, orig)),
                              ("bp", lambda: pbp.bp_decode(code, llr, bp))):
                 torch.cuda.synchronize()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -347,16 +369,19 @@ def alg1_long(torch, pbp, F=8192, snrs=(2.0, 2.5, 3.0)):
                 torch.cuda.synchronize()
                 ms = a.elapsed_time(b)
                 it = res[1].double()
+                e = int((res[0] != m).any(1).sum().item())
                 row[dec] = {"ms": round(ms, 2), "avg_iters": round(it.mean().item(), 2),
                             "max_iters": int(it.max().item()),
                             "frame_it_s": round(it.sum().item() / (ms / 1e3)),
-                            "fer": (res[0] != m).any(1).double().mean().item()}
+                            "fer": e / F, "fer_ci95": [round(v, 6) for v in clopper_pearson(e, F)]}
             points.append(row)
-            _log(f"Algorithm 1 {name} 2e4 set at {snr} dB: fer {row['alg1']['fer']:.4g} "
-                 f"({row['alg1']['ms']} ms) vs BP fer {row['bp']['fer']:.4g} ({row['bp']['ms']} ms)")
+            _log(f"Algorithm 1 {name} 2e4 set at {snr} dB: fer current-graph {row['alg1']['fer']:.4g} "
+                 f"({row['alg1']['ms']} ms), original-graph {row['alg1_orig']['fer']:.4g} "
+                 f"({row['alg1_orig']['ms']} ms), BP {row['bp']['fer']:.4g} ({row['bp']['ms']} ms)")
         out[name] = points
-    return {"workload": f"Algorithm 1 with Table I's 2e4-iteration sets vs plain BP, N_it,max = 20000, "
-                        f"CRC-24, CRC stop from iteration 3, {F} frames per Eb/N0 point", "sets": out}
+    return {"workload": f"Algorithm 1 with Table I's 2e4-iteration sets, subgraph of the current graph (alg1) "
+                        f"and of the original graph (alg1_orig), vs plain BP, N_it,max = 20000, CRC-24, CRC stop "
+                        f"from iteration 3, {F} frames per Eb/N0 point", "sets": out}
 
 
 def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
@@ -370,7 +395,8 @@ def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
     bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC)
     scheds = (("bp", None),
               ("lastk4", pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)),
-              ("alg1", pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)))
+              ("alg1", pbp.PPParams(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)),
+              ("alg1_orig", pbp.PPParams(mode=pbp.PP_ALG1_ORIG, P_range=2, P_level=6, D=8, N_min=4, seed=1)))
     names = ("correct", "false_converged", "oscillation", "unconverged")
     points = []
     for snr in snrs:
@@ -428,7 +454,8 @@ def error_classes(torch, pbp, F=65536, snrs=(1.5, 2.0, 2.5, 3.0), H=32):
             for n, _ in scheds[:2]))
     return {"workload": f"error classes (Sec. II-C) from the last {H} decision hashes, N=1024 K=496+CRC16, "
                         f"{F} frames per Eb/N0 point, max 200 iterations, CRC stop; plain BP, fixed last-4 "
-                        f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4); and N=1024 "
+                        f"(T=10, Q=8), Algorithm 1 (P_range 2, P_level 6, D 8, N_min 4) with subgraphs of "
+                        f"the current graph (alg1) and of the original graph (alg1_orig); and N=1024 "
                         f"K=666 incl. CRC-24 (R=0.65), CRC stop from iteration 3, plain BP and last-4",
             "points": points, "rate_065": rate065}
 
@@ -486,12 +513,15 @@ def noise_aided(torch, pbp, F=65536, sigma=0.6):
         bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
         lastk = dict(mode=pbp.PP_LASTK, k=4, period_T=10, seed=1)
         alg1 = dict(mode=pbp.PP_ALG1, P_range=2, P_level=6, D=8, N_min=4, seed=1)
+        orig = dict(alg1, mode=pbp.PP_ALG1_ORIG)
         scheds = (("bp", pbp.PPParams()),
                   ("lastk4", pbp.PPParams(pool_Q=8, **lastk)),
                   ("lastk4_noise", pbp.PPParams(pool_Q=8, noise_sigma=sigma, **lastk)),
                   ("noise_only", pbp.PPParams(pool_Q=1, noise_sigma=sigma, **lastk)),
                   ("alg1", pbp.PPParams(**alg1)),
-                  ("alg1_noise", pbp.PPParams(noise_sigma=sigma, **alg1)))
+                  ("alg1_noise", pbp.PPParams(noise_sigma=sigma, **alg1)),
+                  ("alg1_orig", pbp.PPParams(**orig)),
+                  ("alg1_orig_noise", pbp.PPParams(noise_sigma=sigma, **orig)))
         for snr in snrs:
             gen = torch.Generator(device="cuda")
             gen.manual_seed(int(snr * 100) + K)
@@ -515,7 +545,8 @@ def noise_aided(torch, pbp, F=65536, sigma=0.6):
     return {"workload": f"noise injected at the events (sigma^2 = {sigma * sigma:.2f}), N=1024, CRC-24, "
                         f"R = 1/2 (K=512) and 0.65 (K=666), {F} frames per point, max 200 iterations, "
                         f"CRC stop from iteration 3, fixed-schedule events every 10 iterations, "
-                        f"Algorithm 1 with the Table I 200-iteration set", "points": out}
+                        f"Algorithm 1 with the Table I 200-iteration set, subgraphs of the current graph "
+                        f"(alg1) and of the original graph (alg1_orig)", "points": out}
 
 
 def n64_gtest(torch, pbp, F=2000, F_sustained=1 << 20, snrs=(1.0, 2.0, 3.0, 4.0)):

@@ -239,10 +239,12 @@ def test_invalid_arguments(pbp):
         pbp.pp_mt_bp_decode(big, l2, pbp.BPParams(), pbp.PPParams(), cfg=pbp.LaunchCfg(2, 4, 0))
 
 
-def test_full_size_n1024_sampled(orc, pbp):
+@pytest.mark.parametrize("snr", [1.5, 2.5, 3.5])
+def test_full_size_n1024_sampled(orc, pbp, snr):
     """The bench workload's shape: 1e6 frames of N = 1024 in one launch with the
-    default launch shape; 256 sampled frames checked one by one against the
-    oracle, and the frame error rate against the oracle's FP64 interval."""
+    default launch shape, at the ends and the middle of the Eb/N0 sweep; 256
+    sampled frames checked one by one against the oracle, and the frame error
+    rate against the oracle's FP64 interval."""
     from scipy.stats import beta
     torch = _torch()
     oc = orc.construct(1024, 512, 2.5, 16, 0x1021)
@@ -253,8 +255,8 @@ def test_full_size_n1024_sampled(orc, pbp):
     idx = torch.arange(F, device="cuda") % pool
     x = torch.from_numpy(xs).cuda()[idx]
     gen = torch.Generator(device="cuda")
-    gen.manual_seed(1234)
-    llr = synth.awgn_llr_torch(x, 2.5, oc.K_msg, gen)
+    gen.manual_seed(1234 + int(snr * 10))
+    llr = synth.awgn_llr_torch(x, snr, oc.K_msg, gen)
     del x
     bp = pbp.BPParams(max_iter=200, stop=pbp.STOP_CRC, it_min=3)
     pp = pbp.PPParams(mode=pbp.PP_LASTK, k=4, period_T=10, pool_Q=8, seed=1)
@@ -272,10 +274,9 @@ def test_full_size_n1024_sampled(orc, pbp):
     # frame errors over all frames against the FP64 oracle on 2000 fresh frames
     want = torch.from_numpy(msgs).cuda()[idx]
     fer_gpu = (msg != want).any(1).double().mean().item()
-    oc_l = synth.awgn_llr(np.repeat(xs[:1], 1, 0), 2.5, oc.K_msg, seed=1)  # warm path
     m2 = synth.message_bits(91, 2000, oc.K_msg)
     _, x2 = orc.encode(oc, m2)
-    l2 = synth.awgn_llr(x2, 2.5, oc.K_msg, seed=91)
+    l2 = synth.awgn_llr(x2, snr, oc.K_msg, seed=91)
     r64 = orc.decode(oc, l2, orc.DecodeParams(max_iter=200, stop=orc.STOP_CRC, it_min=3,
                                               pp_mode=0, k=4, T=10, Q=8, seed=1, fp32=False),
                      threads=8)
@@ -283,7 +284,6 @@ def test_full_size_n1024_sampled(orc, pbp):
     lo = beta.ppf(0.025, e, 2000 - e + 1) if e else 0.0
     hi = beta.ppf(0.975, e + 1, 2000 - e)
     assert lo <= fer_gpu <= hi, (fer_gpu, lo, hi)
-    del oc_l
 
 
 @pytest.mark.parametrize("N,K,cw,poly,mode", [(256, 144, 16, 0x1021, -1), (1024, 512, 16, 0x1021, 0),

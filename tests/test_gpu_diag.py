@@ -91,13 +91,14 @@ def test_history_and_classes_match_oracle(orc, pbp, N, K, cw, poly, F, snr, H, b
     assert wrong.sum() > 0, f"{tag}: the case should contain failed frames"
 
 
-def test_algorithm1_history_matches_oracle(orc, pbp):
+@pytest.mark.parametrize("mode", [2, 3], ids=["current", "orig"])  # PP_ALG1, PP_ALG1_ORIG
+def test_algorithm1_history_matches_oracle(orc, pbp, mode):
     t = TABLE1["N512_Nitmax20000"]
     oc, msg, llr = _frames(orc, 512, 333, 24, 0x1864CFB, 48, 2.0, seed=31)
-    ppk = dict(mode=2, P_range=t["P_range"], P_level=t["P_level"], D=t["D"], N_min=t["N_min"], seed=5)
+    ppk = dict(mode=mode, P_range=t["P_range"], P_level=t["P_level"], D=t["D"], N_min=t["N_min"], seed=5)
     _, _, _, out = _gpu_trace(pbp, oc, llr, 24, dict(max_iter=120, stop=2, it_min=3), ppk)
     m, it, ok, hist = _host(out)
-    p = orc.DecodeParams(max_iter=120, stop=2, it_min=3, pp_mode=2, P_range=t["P_range"],
+    p = orc.DecodeParams(max_iter=120, stop=2, it_min=3, pp_mode=mode, P_range=t["P_range"],
                          P_level=t["P_level"], D=t["D"], N_min=t["N_min"], seed=5, fp32=True)
     ref, rhist = orc.decode_trace(oc, llr, p, 24, threads=8)
     assert np.array_equal(m, ref.msg_hat) and np.array_equal(it, ref.iters)

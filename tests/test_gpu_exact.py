@@ -130,8 +130,9 @@ def test_whole_decodes_agree(orc, pbp, N, K, cw, poly, snr, ppk, opk):
     assert e_gpu <= e_ms + 3 * math.sqrt(max(e_ms, 1)), (e_gpu, e_ms)
 
 
+@pytest.mark.parametrize("mode", [2, 3], ids=["current", "orig"])  # PP_ALG1, PP_ALG1_ORIG
 @pytest.mark.parametrize("iters,first_reset", [(1, 0), (3, 1), (5, 2)])
-def test_algorithm1_early_messages_within_rounding(orc, pbp, iters, first_reset):
+def test_algorithm1_early_messages_within_rounding(orc, pbp, iters, first_reset, mode):
     # Algorithm 1 with the exact boxplus: its events depend on the draws only,
     # so both sides permute the same blocks; the u-side messages after a few
     # iterations (events after iterations 1 and 2 included) within rounding
@@ -142,17 +143,18 @@ def test_algorithm1_early_messages_within_rounding(orc, pbp, iters, first_reset)
     llr = synth.awgn_llr(x, 1.5, oc.K_msg, seed=300 + iters)
     bp = pbp.BPParams(max_iter=iters, stop=pbp.STOP_NONE, check=pbp.CHECK_EXACT)
     t = dict(P_range=5, P_level=4, D=0, N_min=1, first_reset=first_reset, seed=4)
-    soft = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=pbp.PP_ALG1, **t))[3]
+    soft = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=mode, **t))[3]
     ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=iters, stop=orc.STOP_NONE, fp32=False,
-                                               exact_boxplus=True, pp_mode=orc.PP_ALG1, **t),
+                                               exact_boxplus=True, pp_mode=mode, **t),
                      soft=True, threads=8)
     scale = np.maximum(np.abs(ref.soft_u), np.abs(llr).max(1, keepdims=True))
     ratio = np.abs(soft - ref.soft_u) / scale
     assert ratio.max() <= TOL, f"max relative deviation {ratio.max():.3e}"
 
 
+@pytest.mark.parametrize("mode", [2, 3], ids=["current", "orig"])  # PP_ALG1, PP_ALG1_ORIG
 @pytest.mark.parametrize("N,K,table", [(512, 333, (9, 8, 50, 15)), (1024, 512, (2, 6, 8, 4))])
-def test_algorithm1_whole_decodes_agree(orc, pbp, N, K, table):
+def test_algorithm1_whole_decodes_agree(orc, pbp, N, K, table, mode):
     # Table I parameter sets with the exact boxplus.  The events reset parts
     # of the graph every few iterations, which lets rounding-level differences
     # steer slowly converging frames apart (they stop at another iteration,
@@ -164,9 +166,9 @@ def test_algorithm1_whole_decodes_agree(orc, pbp, N, K, table):
     P_range, P_level, D, N_min = table
     t = dict(P_range=P_range, P_level=P_level, D=D, N_min=N_min, seed=6)
     bp = pbp.BPParams(max_iter=150, stop=pbp.STOP_CRC, it_min=3, check=pbp.CHECK_EXACT)
-    m, it, ok, _ = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=pbp.PP_ALG1, **t))
+    m, it, ok, _ = _gpu(pbp, oc, llr, bp, pbp.PPParams(mode=mode, **t))
     ref = orc.decode(oc, llr, orc.DecodeParams(max_iter=150, stop=orc.STOP_CRC, it_min=3, fp32=False,
-                                               exact_boxplus=True, pp_mode=orc.PP_ALG1, **t), threads=8)
+                                               exact_boxplus=True, pp_mode=mode, **t), threads=8)
     same = (m == ref.msg_hat).all(1) & (it == ref.iters) & (ok == ref.ok)
     stopped = ref.ok == 1
     early = stopped & (ref.iters <= 20)

@@ -107,7 +107,8 @@ def test_noise_on_the_large_workload_sampled(orc, pbp):
     assert np.array_equal(it[pick], ref.iters[pick]) and np.array_equal(ok[pick], ref.ok[pick])
 
 
-def test_algorithm1_noise_on_the_large_workload_sampled(orc, pbp):
+@pytest.mark.parametrize("mode", [2, 3], ids=["current", "orig"])  # PP_ALG1, PP_ALG1_ORIG
+def test_algorithm1_noise_on_the_large_workload_sampled(orc, pbp, mode):
     # Algorithm 1 (Table I 200-iteration set) with noise at its events, 16384
     # frames of the 1024-bit code in one launch (two frames per CU, refills
     # from the queue); sampled frames of a prefix against the oracle
@@ -115,11 +116,11 @@ def test_algorithm1_noise_on_the_large_workload_sampled(orc, pbp):
     oc, msg, llr = _frames(orc, 1024, 512, 24, 0x1864CFB, F, 2.0, seed=8)
     bpk = dict(max_iter=200, stop=2, it_min=3)
     t = dict(P_range=2, P_level=6, D=8, N_min=4, seed=4)
-    m, it, ok = _gpu(pbp, oc, llr, bpk, dict(mode=2, noise_sigma=0.6, **t), soft=False)
+    m, it, ok = _gpu(pbp, oc, llr, bpk, dict(mode=mode, noise_sigma=0.6, **t), soft=False)
     P = 1024
     rng = np.random.default_rng(4)
     pick = np.union1d(rng.choice(P, 40, replace=False), np.argsort(-it[:P])[:8])
-    ref = orc.decode(oc, llr[:P], orc.DecodeParams(max_iter=200, stop=2, it_min=3, pp_mode=2, fp32=True,
+    ref = orc.decode(oc, llr[:P], orc.DecodeParams(max_iter=200, stop=2, it_min=3, pp_mode=mode, fp32=True,
                                                    noise_sigma=0.6, **t), threads=8)
     assert np.array_equal(m[pick], ref.msg_hat[pick])
     assert np.array_equal(it[pick], ref.iters[pick]) and np.array_equal(ok[pick], ref.ok[pick])
