@@ -186,6 +186,13 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
     // stage s through them (bit s), and which of A (bit 0) and B (bit 1) need a
     // workgroup barrier (an exchange within each wave needs none); uniform
     uint32_t lmask = 0u, rmask = 0u, abar = 0u;
+    // A block of two stages (rho_range = 2) swaps bits rl-1 and rl, which in a
+    // thread's pair is the butterfly on element bit rl-1 (element bit and slot
+    // trade places).  Where that element bit sits on a lane bit, the block's
+    // boundaries take that butterfly on the block's threads (fast: bit 0 A,
+    // bit 1 B; lane bits kA, kB) in place of the exchange through LDS.
+    uint32_t fast = 0u;
+    int kA = 0, kB = 0;
     // alternating buffer of the exchanges with a barrier
     int xsel = 0;
     auto slot = [&](int b, int j) -> int {
@@ -205,6 +212,28 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
     // stage m+1 hold one row of each.  Every other thread keeps its butterfly.
     auto in_a = [&](int e) -> bool { return (e >> (m - 1)) == blk; };
     auto in_b = [&](int e) -> bool { return (e >> m) == (blk >> 1); };
+    // the lane bit that carries element bit k at stage s (6 and up: a wave bit)
+    auto lane_bit = [&](int k, int s) -> int {
+        if constexpr (W == 0) {
+            return k;
+        } else if (s <= 6) {
+            return k <= 4 ? k + 1 : k == 5 ? 0 : 6;
+        } else {
+            return k <= 2 ? k : (k >= 6 && k < 6 + W) ? 3 + (k - 6) : 3 + W + (k - 3);
+        }
+    };
+    // the butterfly on lane bit k (uniform), kept by the threads with sel; the
+    // partner's value comes by ds_bpermute (one code path for every k)
+    auto conv = [&](float &v0, float &v1, int k, bool sel) {
+        const bool b = (lane >> k) & 1;
+        const int recv = __builtin_amdgcn_ds_bpermute((lane ^ (1 << k)) << 2, __float_as_int(b ? v0 : v1));
+        if (sel) {
+            if (b)
+                v0 = __int_as_float(recv);
+            else
+                v1 = __int_as_float(recv);
+        }
+    };
     // the exchange slots and masks for the current block (the C slots again
     // only if redo_c); the barrier needs are published as wave flags in
     // misc[32 + w] (read after the caller's next barrier)
@@ -213,6 +242,12 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
         bool ca = false, cb = false;
         const bool hasA = m > 0 && rl >= 2 && !(W > 0 && rl - 1 == 6);
         const bool hasB = m > 0 && m < n && !(W > 0 && m == 6);
+        fast = 0u;
+        if (rr == 2) {
+            kA = lane_bit(rl - 1, rl);
+            kB = lane_bit(rl - 1, m);
+            fast = (hasA && kA < 6 ? 1u : 0u) | (hasB && kB < 6 ? 2u : 0u);
+        }
         if (hasA) {
             lmask |= 1u << (rl - 1);
             rmask |= 1u << rl;
@@ -224,11 +259,11 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
         if (pe) {
             if constexpr (W > 0)
                 if (redo_c) cS = slots(6);
-            if (hasA && in_a(elem(rl - 1))) {
+            if (hasA && !(fast & 1u) && in_a(elem(rl - 1))) {
                 aS = slots(rl - 1);
                 ca = crosses(aS);
             }
-            if (hasB && in_b(elem(m))) {
+            if (hasB && !(fast & 2u) && in_b(elem(m))) {
                 bS = slots(m);
                 cb = crosses(bS);
             }
@@ -372,10 +407,20 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
                         if (__builtin_expect((lmask >> s) & 1u, 0)) {
                             float u0 = lt, u1 = lb;
                             bfly_wave<K>(u0, u1, lane);
-                            if (s == rl - 1)
-                                exchange(lt, lb, u0, u1, aS, abar & 1u, false, pe && in_a(elem(s)));
-                            else
+                            if (s == rl - 1) {
+                                if (fast & 1u)  // into a two-stage block's coordinates
+                                    conv(lt, lb, kA, in_a(elem(s)));
+                                else
+                                    exchange(lt, lb, u0, u1, aS, abar & 1u, false, pe && in_a(elem(s)));
+                            } else if (fast & 2u) {
+                                // out of a two-stage block: back to row order, then the butterfly
+                                conv(u0, u1, kB, in_a(elem(s)));
+                                lt = u0;
+                                lb = u1;
+                                bfly_wave<K>(lt, lb, lane);
+                            } else {
                                 exchange(lt, lb, u0, u1, bS, abar & 2u, false, pe && in_b(elem(s)));
+                            }
                         }
                     }
                     Li[s + 1][0] = lt;
@@ -439,10 +484,21 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 4) k_alg1o(Alg1Args a
                     if (__builtin_expect((rmask >> s) & 1u, 0)) {
                         float u0 = rt, u1 = rb;
                         bfly_wave<K>(u0, u1, lane);
-                        if (s == rl)
-                            exchange(rt, rb, u0, u1, aS, abar & 1u, true, pe && in_a(elem(s)));
-                        else
+                        if (s == rl) {
+                            if (fast & 1u) {
+                                // out of a two-stage block: back to row order, then the butterfly
+                                conv(u0, u1, kA, in_a(elem(s)));
+                                rt = u0;
+                                rb = u1;
+                                bfly_wave<K>(rt, rb, lane);
+                            } else {
+                                exchange(rt, rb, u0, u1, aS, abar & 1u, true, pe && in_a(elem(s)));
+                            }
+                        } else if (fast & 2u) {
+                            conv(rt, rb, kB, in_a(elem(s)));  // into a two-stage block's coordinates
+                        } else {
                             exchange(rt, rb, u0, u1, bS, abar & 2u, true, pe && in_b(elem(s)));
+                        }
                     }
                 }
                 Ri[s - 1][0] = rt;
