@@ -49,8 +49,19 @@ struct WbpArgs {
     int8_t orders[8][16];
 };
 
-__device__ __forceinline__ float ms0(float x, float y) { return cnode<false>(x, y, 1.f); }
-__device__ __forceinline__ float sgnf(float v) { return (__float_as_uint(v) >> 31) ? -1.f : 1.f; }
+// Min-sum check function in clamp form (two instructions), b the operand that
+// bounds the other: equal to sgn(b) sgn(y) min(|b|,|y|) wherever that is
+// nonzero.  A zero result (an input zero) may carry the other sign; no
+// derivative below reads the sign of such a zero (a sign is read only from
+// an operand of larger magnitude than another, or from an L message or a sum
+// with one, which the channel's nonzero LLRs keep nonzero), so outputs and
+// gradients are those of the sign-magnitude form.
+__device__ __forceinline__ float ms0c(float b, float y) { return cnode_clamp<0>(b, y, 1.f); }
+// d sgn(s) with sgn(s) = -1 when the sign bit of s is set (also for -0), else
+// +1: the sign bit of d flipped by that of s, one v_bitop3_b32
+__device__ __forceinline__ float xsign(float d, float s) {
+    return __uint_as_float(__float_as_uint(d) ^ (__float_as_uint(s) & 0x80000000u));
+}
 
 // LDS per slot.  Forward: the L and R boundary ping-pong pairs (4N floats).
 // Adjoint: the same two pairs, reused by the reverse sweeps for the adjoint
@@ -150,8 +161,8 @@ __device__ __forceinline__ void wgroup_L(const float (&lbot)[P::ROWS], float (&l
                 if constexpr (sl + 1 < r) { r1 = rint[sl][i]; r2 = rint[sl][ip]; }
                 else { r1 = rtop[i]; r2 = rtop[ip]; }
                 const float l1 = cur[i], l2 = cur[ip];
-                nxt[i] = wv[i] * ms0(l1, l2 + r2);
-                nxt[ip] = wv[ip] * ms0(r1, l1) + l2;
+                nxt[i] = wv[i] * ms0c(l1, l2 + r2);
+                nxt[ip] = wv[ip] * ms0c(l1, r1) + l2;
             }
         });
         if constexpr (sl + 1 < r) sfor<0, ROWS>([&](auto i) { lint[sl][i] = nxt[i]; });
@@ -180,8 +191,8 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
                 if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 const float r1 = cur[i], r2 = cur[ip];
-                nxt[i] = wv[i] * ms0(r1, l2 + r2);
-                nxt[ip] = wv[ip] * ms0(r1, l1) + r2;
+                nxt[i] = wv[i] * ms0c(l2 + r2, r1);
+                nxt[ip] = wv[ip] * ms0c(l1, r1) + r2;
             }
         });
         if constexpr (sl > 0) sfor<0, ROWS>([&](auto i) { rint[sl - 1][i] = nxt[i]; });
@@ -192,12 +203,16 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
 
 // ---- reverse passes ------------------------------------------------------
 // Reverse of the weighted R pass of group g.  gbot: adjoint of the R message
-// this group produces on its bottom level.  gstate: adjoint, from the next
-// iteration, of the R messages it produces on its interior levels.  Adds the
-// adjoints of the L messages it read into glint/glbot, returns in gtop the
-// adjoint of the R message it read on its top level, and stages the weight
-// gradients of its stages (sweep 1) through gw(stage - lo, row offset, value).
-template <class P, int g, class Sink>
+// this group produces on its bottom level (ZBOT: known to be zero, the
+// channel level's R, which nothing reads).  gstate: adjoint, from the next
+// iteration, of the R messages it produces on its interior levels.  Writes
+// the adjoints of the L messages it read into glint/glbot (every entry once),
+// returns in gtop the adjoint of the R message it read on its top level, and
+// stages the weight gradients of its stages (sweep 1) through
+// gw(stage - lo, row offset, value).  The derivative routing is the min-sum
+// rule of the forward's check function, written branch-free: a select per
+// route and the sign flips as bit operations.
+template <class P, int g, bool ZBOT, class Sink>
 __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
                                             const float (&gbot)[P::ROWS], const float (&gstate)[P::RI][P::ROWS],
@@ -206,8 +221,16 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     float gacc[P::RI][ROWS];
     sfor<0, r - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { gacc[l][i] = gstate[l][i]; }); });
-    sfor<0, ROWS>([&](auto i) { gtop[i] = 0.f; });
     sfor<0, r>([&](auto sl) {
+        if constexpr (ZBOT && sl == 0) {
+            // a zero adjoint: zero weight gradients, nothing flows on
+            sfor<0, ROWS>([&](auto i) {
+                gw(0, GMap<P, g>::off(i), 0.f);
+                glbot[i] = 0.f;
+                if constexpr (r == 1) gtop[i] = 0.f;
+            });
+            return;
+        }
         float go[ROWS];
         if constexpr (sl == 0) sfor<0, ROWS>([&](auto i) { go[i] = gbot[i]; });
         else sfor<0, ROWS>([&](auto i) { go[i] = gacc[sl - 1][i]; });
@@ -222,45 +245,49 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
                 else { r1 = rtopsw[i]; r2 = rtopsw[ip]; }
                 if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
+                // outputs: R'1 = w1 ms(r1, l2 + r2), R'2 = w2 ms(r1, l1) + r2
                 const float a = l2 + r2;
-                const float g1 = ms0(r1, a), g2 = ms0(r1, l1);
-                gw(sl, GMap<P, g>::off(i), go[i] * g1);
-                gw(sl, GMap<P, g>::off(ip), go[ip] * g2);
+                gw(sl, GMap<P, g>::off(i), go[i] * ms0c(a, r1));
+                gw(sl, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
-                float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
-                if (__builtin_fabsf(r1) <= __builtin_fabsf(a)) {
-                    gr1 = d1 * sgnf(a);
-                } else {
-                    const float ga = d1 * sgnf(r1);
-                    gl2 = ga;
-                    gr2 = ga;
-                }
-                if (__builtin_fabsf(r1) <= __builtin_fabsf(l1)) gr1 += d2 * sgnf(l1);
-                else gl1 = d2 * sgnf(r1);
-                gr2 += go[ip];
+                const bool c1 = __builtin_fabsf(r1) <= __builtin_fabsf(a);
+                const bool c2 = __builtin_fabsf(r1) <= __builtin_fabsf(l1);
+                const float ga = c1 ? 0.f : xsign(d1, r1);  // to l2 and r2
+                const float gr1 = (c1 ? xsign(d1, a) : 0.f) + (c2 ? xsign(d2, l1) : 0.f);
+                const float gl1 = c2 ? 0.f : xsign(d2, r1);
+                const float gr2 = ga + go[ip];
                 if constexpr (sl + 1 < r) { gacc[sl][i] += gr1; gacc[sl][ip] += gr2; }
-                else { gtop[i] += gr1; gtop[ip] += gr2; }
-                if constexpr (sl > 0) { glint[sl - 1][i] += gl1; glint[sl - 1][ip] += gl2; }
-                else { glbot[i] += gl1; glbot[ip] += gl2; }
+                else { gtop[i] = gr1; gtop[ip] = gr2; }
+                if constexpr (sl > 0) { glint[sl - 1][i] = gl1; glint[sl - 1][ip] = ga; }
+                else { glbot[i] = gl1; glbot[ip] = ga; }
             }
         });
     });
 }
 
 // Reverse of the weighted L pass of group g.  gtop: adjoint of the L message
-// it produced on its top level; glint: adjoints (already holding the R-sweep
-// contributions) of its interior L messages.  Adds to glbot, adds the
-// adjoints of the entering R state it read into gsint/gstop, stages the
-// weight gradients of its stages (sweep 0) through gw(stage - lo, row offset, value).
-template <class P, int g, bool TOPPRIOR, class Sink>
+// it produced on its top level (ZTOP: known to be zero, the decision level's
+// L before the last iteration); glint: adjoints (already holding the R-sweep
+// contributions) of its interior L messages.  Adds to glbot, writes the
+// adjoints of the entering R state it read into gsint/gstop (every entry
+// once; gstop untouched when the top level is the prior), stages the weight
+// gradients of its stages (sweep 0) through gw(stage - lo, row offset, value).
+template <class P, int g, bool TOPPRIOR, bool ZTOP, class Sink>
 __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
                                             const float (&gtop)[P::ROWS], float (&glint)[P::RI][P::ROWS],
                                             float (&glbot)[P::ROWS], float (&gsint)[P::RI][P::ROWS],
                                             float (&gstop)[P::ROWS], const float *wg, Sink &&gw) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
+    static_assert(!ZTOP || TOPPRIOR, "a zero top adjoint is the last group's");
     sfor<0, r>([&](auto k) {
         constexpr int sl = r - 1 - k;
+        if constexpr (ZTOP && sl == r - 1) {
+            // a zero adjoint on the prior-topped stage: zero weight gradients
+            // and nothing flows on (its R side is the prior)
+            sfor<0, ROWS>([&](auto i) { gw(sl, GMap<P, g>::off(i), 0.f); });
+            return;
+        }
         float go[ROWS];
         if constexpr (sl == r - 1) sfor<0, ROWS>([&](auto i) { go[i] = gtop[i]; });
         else sfor<0, ROWS>([&](auto i) { go[i] = glint[sl][i]; });
@@ -275,26 +302,21 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
                 else { r1 = rtop[i]; r2 = rtop[ip]; }
                 if constexpr (sl > 0) { l1 = lint[sl - 1][i]; l2 = lint[sl - 1][ip]; }
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
+                // outputs: L'1 = w1 ms(l1, l2 + r2), L'2 = w2 ms(r1, l1) + l2
                 const float a = l2 + r2;
-                const float f1 = ms0(l1, a), f2 = ms0(r1, l1);
-                gw(sl, GMap<P, g>::off(i), go[i] * f1);
-                gw(sl, GMap<P, g>::off(ip), go[ip] * f2);
+                gw(sl, GMap<P, g>::off(i), go[i] * ms0c(l1, a));
+                gw(sl, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
-                float gr1 = 0.f, gr2 = 0.f, gl1 = 0.f, gl2 = 0.f;
-                if (__builtin_fabsf(l1) <= __builtin_fabsf(a)) {
-                    gl1 = d1 * sgnf(a);
-                } else {
-                    const float ga = d1 * sgnf(l1);
-                    gl2 = ga;
-                    gr2 = ga;
-                }
-                if (__builtin_fabsf(r1) <= __builtin_fabsf(l1)) gr1 = d2 * sgnf(l1);
-                else gl1 += d2 * sgnf(r1);
-                gl2 += go[ip];
+                const bool c1 = __builtin_fabsf(l1) <= __builtin_fabsf(a);
+                const bool c2 = __builtin_fabsf(r1) <= __builtin_fabsf(l1);
+                const float ga = c1 ? 0.f : xsign(d1, l1);  // to l2 and r2
+                const float gl1 = (c1 ? xsign(d1, a) : 0.f) + (c2 ? 0.f : xsign(d2, r1));
+                const float gr1 = c2 ? xsign(d2, l1) : 0.f;
+                const float gl2 = ga + go[ip];
                 if constexpr (sl > 0) { glint[sl - 1][i] += gl1; glint[sl - 1][ip] += gl2; }
                 else { glbot[i] += gl1; glbot[ip] += gl2; }
-                if constexpr (sl + 1 < r) { gsint[sl][i] += gr1; gsint[sl][ip] += gr2; }
-                else if constexpr (!TOPPRIOR) { gstop[i] += gr1; gstop[ip] += gr2; }
+                if constexpr (sl + 1 < r) { gsint[sl][i] = gr1; gsint[sl][ip] = ga; }
+                else if constexpr (!TOPPRIOR) { gstop[i] = gr1; gstop[ip] = ga; }
             }
         });
     });
@@ -564,10 +586,14 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     });
                 }
             }
-            sfor<0, G>([&](auto g) {
-                sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[g][l][i] = 0.f; }); });
-                sfor<0, ROWS>([&](auto i) { glb[g][i] = 0.f; });
-            });
+            // the reverse R sweep writes the L adjoints; without it (the last
+            // iteration) they start at zero
+            if (lastit) {
+                sfor<0, G>([&](auto g) {
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[g][l][i] = 0.f; }); });
+                    sfor<0, ROWS>([&](auto i) { glb[g][i] = 0.f; });
+                });
+            }
         }
         // ---- recompute the L sweep ----
         sfor<0, G - 1>([&](auto g) {
@@ -643,7 +669,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2 + 1) * N + base
                                             : buf + 4 * N + (g & 1) * RHO * N + base;
                     constexpr int SLS = WAVE ? 2 * N : N;
-                    rev_group_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
+                    rev_group_R<P, g, g == 0>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
                                       wt + base, [&](int sl, int off, float v) { gws[sl * SLS + off] = v; });
                     if constexpr (g < G - 1) {
                         float *dst = buf + ((g + 1) & 1) * N;
@@ -653,12 +679,8 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                 boundary_sync<WAVE>();
             });
         }
-        // the new state adjoint comes only from the reverse L sweep
-        sfor<0, G>([&](auto g) {
-            sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
-            sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
-        });
-        // ---- reverse of the L sweep: groups top to bottom ----
+        // ---- reverse of the L sweep: groups top to bottom (it writes the new
+        // state adjoint, every entry the reverse R sweep reads) ----
         const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
         sfor<0, G>([&](auto k) {
             constexpr int g = G - 1 - k;
@@ -674,16 +696,22 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
             if (active) {
                 const int base = GMap<P, g>::base(t);
                 float gt[ROWS];
+                auto sink = [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; };
                 if constexpr (g == G - 1) {
-                    if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
-                    else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
-                    rev_group_L<P, g, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g], gsi[g],
-                                            gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; });
+                    // the output adjoint enters at the last iteration only
+                    if (lastit) {
+                        sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
+                        rev_group_L<P, g, true, false>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
+                                                       gsi[g], gst[g], wt + base, sink);
+                    } else {
+                        rev_group_L<P, g, true, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
+                                                      gsi[g], gst[g], wt + base, sink);
+                    }
                 } else {
                     const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
-                    rev_group_L<P, g, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g], glb[g],
-                                             gsi[g], gst[g], wt + base, [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; });
+                    rev_group_L<P, g, false, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g],
+                                                    glb[g], gsi[g], gst[g], wt + base, sink);
                 }
                 if constexpr (g > 0) {
                     float *dst = buf + 2 * N + (g & 1) * N;
@@ -888,7 +916,7 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     }
                     sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = 0.f; }); });
                     sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
-                    rev_group_R<P, g>(lbot, lint, rsw, rtsw, gb, gsi, gli, glb, gtop, wt + base,
+                    rev_group_R<P, g, g == 0>(lbot, lint, rsw, rtsw, gb, gsi, gli, glb, gtop, wt + base,
                                       sink(P::lo(g), 1, base));
                     store2(GL, g, gli, glb);
                     if constexpr (g < G - 1) {
@@ -920,15 +948,20 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                 sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[l][i] = 0.f; }); });
                 sfor<0, ROWS>([&](auto i) { gst[i] = 0.f; });
                 if constexpr (g == G - 1) {
-                    if (lastit) sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
-                    else sfor<0, ROWS>([&](auto i) { gt[i] = 0.f; });
-                    rev_group_L<P, g, true>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
-                                            sink(P::lo(g), 0, base));
+                    // the output adjoint enters at the last iteration only
+                    if (lastit) {
+                        sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
+                        rev_group_L<P, g, true, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
+                                                       sink(P::lo(g), 0, base));
+                    } else {
+                        rev_group_L<P, g, true, true>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
+                                                      sink(P::lo(g), 0, base));
+                    }
                 } else {
                     const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
-                    rev_group_L<P, g, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
-                                             sink(P::lo(g), 0, base));
+                    rev_group_L<P, g, false, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
+                                                    sink(P::lo(g), 0, base));
                 }
                 store2(GS, std::integral_constant<int, g>{}, gsi, gst);
                 if constexpr (g > 0) {
