@@ -25,11 +25,10 @@ inline int wbp_bwd_slots_n(int n) {
     return tps <= 64 ? 512 / tps : wbp_slots(n);
 }
 
-// Block lengths from 2^kWbpBigLog on run the adjoint with its arrays in a
-// per-workgroup scratch (k_wbp_bwd_big) on a persistent grid of this many
-// workgroups (one per CU at N = 4096, two at N = 2048); fixed, so that the
-// order of the gradient sums does not depend on the device.
-constexpr int kWbpBigLog = 11;
+// Block lengths from 2^kWbpBigLog on (wbp_kernel.h) run the adjoint with its
+// arrays in a per-workgroup scratch (k_wbp_bwd_big) on a persistent grid of
+// this many workgroups (one per CU at N = 4096, two at N = 2048); fixed, so
+// that the order of the gradient sums does not depend on the device.
 inline int wbp_big_grid(int n) { return n >= 12 ? 256 : 512; }
 size_t wbp_big_scratch_floats(int n);
 
