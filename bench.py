@@ -79,18 +79,42 @@ def calib_copy(torch):
     print(json.dumps({"calib_copy_bytes": 2 ** 30, "copies": 4}), flush=True)
 
 
-def calibrate(torch):
+def calibrate(torch, chains=False):
     """Measured roofline constants: the VALU issue rate of the decoder's
     instruction mix (add, v_med3_f32, v_bitop3_b32; 48 per loop trip) and the
     LDS read bandwidth (conflict-free 16-byte reads), from the kernels of
-    libpbp_peak.so, each timed with HIP events on torch's stream."""
+    libpbp_peak.so, each timed with HIP events on torch's stream.  chains:
+    also the mix with the decoder's own dependencies (2, 4 or 8 rows per
+    thread) at 1, 2, 4 and 8 waves per SIMD."""
     import ctypes
     path = os.path.join(ROOT, "paper_1911_08868_amd", "libpbp_peak.so")
     L = ctypes.CDLL(path)
     L.pbp_peak_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     L.pbp_peak_launch.restype = ctypes.c_int
+    L.pbp_peak_launch_pe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    L.pbp_peak_launch_pe.restype = ctypes.c_int
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     res = {}
+    if chains:
+        tab = {}
+        for rows in (2, 4, 8):
+            for w in (1, 2, 4, 8):
+                blocks, steps = 256 * w * 4, 4000
+                out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+                ms = []
+                for rep in range(3):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    rc = L.pbp_peak_launch_pe(rows, w, blocks, steps, ctypes.c_void_p(out.data_ptr()), stream)
+                    b.record()
+                    torch.cuda.synchronize()
+                    if rc != 0:
+                        raise RuntimeError(f"chain calibration rows {rows} waves {w}: HIP error {rc}")
+                    ms.append(a.elapsed_time(b))
+                ops = blocks * 256 * steps * 8 * (rows // 2) * 6
+                tab[f"rows{rows}_waves{w}"] = round(ops / (min(ms) / 1e3) / 1e12, 2)
+        res["pe_chain_TOPs"] = tab
     for which, blocks, threads, steps in ((0, 256 * 8, 256, 20000), (1, 256 * 2, 1024, 5000),
                                           (2, 256 * 8, 256, 15000), (3, 256 * 8, 256, 15000),
                                           (4, 256 * 8, 256, 15000)):
@@ -273,7 +297,7 @@ def main():
         calib_copy(torch)
         return
     if args.calibrate:
-        print(json.dumps(calibrate(torch)), flush=True)
+        print(json.dumps(calibrate(torch, chains=True)), flush=True)
         return
     if args.extra:
         import bench_workloads

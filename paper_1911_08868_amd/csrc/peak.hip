@@ -113,9 +113,77 @@ __global__ void __launch_bounds__(1024) k_lds(uint32_t *out, int steps) {
     out[blockIdx.x * blockDim.x + threadIdx.x] = x0 ^ x1;
 }
 
+// The processing element with the decoder's own dependencies: ROWS values
+// per thread, per stage ROWS/2 elements on the pairs (i, i | b) of register
+// rows (b cycling over the thread's row bits as the decoder's stages do),
+// each element's two outputs f(x_ip + r_ip, x_i) and f(x_i, r_i) + x_ip from
+// the stage's inputs; 8 stages per loop trip, 6 VALU instructions per
+// element.  Launched with dynamic LDS that caps the workgroups (one wave per
+// SIMD each) per CU, it measures the mix's issue rate against independent
+// chains per wave and waves per SIMD.
+__device__ __forceinline__ float clamp_cn(float b, float y) {
+    const float ab = __builtin_fabsf(b);
+    const float t = __builtin_amdgcn_fmed3f(y, ab, -ab);
+    return __uint_as_float(__float_as_uint(t) ^ (__float_as_uint(b) & 0x80000000u));
+}
+
+template <int ROWS>
+__global__ void __launch_bounds__(256) k_pe_chain(float *out, int steps, float seed) {
+    constexpr int LOG = ROWS == 2 ? 1 : ROWS == 4 ? 2 : 3;
+    float v[ROWS], r[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+        v[i] = seed + (float)(threadIdx.x + 3 * i) - 100.f;
+        r[i] = 0.5f * (float)(i + 1) - 1.3f;
+    }
+    for (int s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int b = 1 << (st % LOG);
+            float nx[ROWS];
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                if ((i & b) == 0) {
+                    const int ip = i | b;
+                    nx[i] = clamp_cn(v[ip] + r[ip], v[i]);
+                    nx[ip] = clamp_cn(v[i], r[i]) + v[ip];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) v[i] = nx[i];
+        }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) acc += v[i];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+// k_pe_chain<rows> (rows 2, 4 or 8) in workgroups of 256 threads with
+// (160 KiB / waves_per_simd - 1 KiB) of dynamic LDS, so that at most
+// waves_per_simd (1..8) workgroups share a CU; `blocks` workgroups, `steps`
+// loop trips, d_out at least blocks * 256 floats.  Returns 0 or the HIP error.
+int pbp_peak_launch_pe(int rows, int waves_per_simd, int blocks, int steps, void *d_out, void *stream) {
+    if (waves_per_simd < 1 || waves_per_simd > 8) return (int)hipErrorInvalidValue;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int lds = (160 * 1024) / waves_per_simd - 1024;
+    const void *k = rows == 2 ? (const void *)k_pe_chain<2> : rows == 4 ? (const void *)k_pe_chain<4>
+                                                                        : (const void *)k_pe_chain<8>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return (int)e;
+    float *o = static_cast<float *>(d_out);
+    if (rows == 2)
+        hipLaunchKernelGGL(k_pe_chain<2>, dim3(blocks), dim3(256), lds, s, o, steps, 0.5f);
+    else if (rows == 4)
+        hipLaunchKernelGGL(k_pe_chain<4>, dim3(blocks), dim3(256), lds, s, o, steps, 0.5f);
+    else
+        hipLaunchKernelGGL(k_pe_chain<8>, dim3(blocks), dim3(256), lds, s, o, steps, 0.5f);
+    return (int)hipGetLastError();
+}
 
 // which = 0: k_valu (workgroups of 256 threads), 1: k_lds (workgroups of 1024
 // threads, 16 waves, so that two workgroups keep 8 waves per SIMD reading
