@@ -98,7 +98,8 @@ static WbpLayout wbp_layout(const pc_code *c, int64_t F, int T) {
     w.slots = wbp_slots(c->n);
     w.bslots = wbp_bwd_slots_n(c->n);
     const bool big = c->n >= kWbpBigLog;
-    w.groups = big ? std::min<int64_t>(F, wbp_big_grid(c->n)) : (F + w.bslots - 1) / w.bslots;
+    w.groups = big ? std::min<int64_t>(F, wbp_big_grid(c->n))
+                   : std::min<int64_t>((F + w.bslots - 1) / w.bslots, wbp_small_grid(c->n));
     w.ckpt_bytes = align256((size_t)F * (size_t)(T > 1 ? T - 1 : 0) * (size_t)(c->n - 1) * c->N * sizeof(float));
     const size_t len = (size_t)T * c->n * 2 * (size_t)c->N;
     w.partial_bytes = align256((size_t)w.groups * len * sizeof(float));
@@ -162,7 +163,7 @@ static int wbp_common(const pc_code *c, const float *d_llr, int64_t F, const flo
     L.slots = lay.slots;
     L.bslots = lay.bslots;
     // the forward takes one workgroup per `slots` frames; the adjoint one per
-    // partial (the persistent grid for large frames)
+    // partial (a fixed grid whose workgroups walk the frames)
     L.grid = (int)((F + lay.slots - 1) / lay.slots);
     L.bgrid = (int)lay.groups;
     return PC_OK;

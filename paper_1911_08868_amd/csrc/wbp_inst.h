@@ -30,6 +30,10 @@ inline int wbp_bwd_slots_n(int n) {
 // this many workgroups (one per CU at N = 4096, two at N = 2048); fixed, so
 // that the order of the gradient sums does not depend on the device.
 inline int wbp_big_grid(int n) { return n >= 12 ? 256 : 512; }
+// Below that the adjoint's grid is fixed too: as many workgroups as the chip
+// holds at once at N <= 256 (one per CU: their frames fill its LDS) and twice
+// that above; each walks batches of its slot count, adding into its partial.
+inline int wbp_small_grid(int n) { return n <= 8 ? 256 : 512; }
 size_t wbp_big_scratch_floats(int n);
 
 template <int NLOG, int KP>

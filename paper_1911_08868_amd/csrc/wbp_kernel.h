@@ -474,8 +474,9 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     constexpr int RI = P::RI;
     constexpr bool WAVE = wbp_wave_frame<P>();
     const int tid = threadIdx.x, S = blockDim.x / TPS, slot = tid / TPS, t = tid & (TPS - 1);
-    const int64_t frame0 = (int64_t)blockIdx.x * S, frame = frame0 + slot;
-    const bool active = frame < a.F;
+    // batches of S consecutive frames; workgroup w takes batches w, w + grid,
+    // ... in that order and adds each batch's gradients into its partial
+    const int64_t nbatch = (a.F + S - 1) / S;
     constexpr size_t PS = WbpLds<P, true>::per_slot / sizeof(float);
     extern __shared__ __align__(16) float smem[];
     // [A0 A1 | B0 B1 | W]: L and R boundary pairs of the recomputed sweeps;
@@ -492,10 +493,6 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     float gli[G][RI][ROWS], glb[G][ROWS];   // adjoints of the L messages
     int baddr[ROWS], toprow[ROWS];
     uint32_t frozen_bits = 0;
-    sfor<0, G>([&](auto g) {
-        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
-        sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
-    });
     auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
     // Sum the weight gradients that one reverse step (group g, sweep d)
     // staged in W[par] over the workgroup's frames, in slot order, and store
@@ -507,243 +504,261 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     // entries per thread (16-byte LDS reads and global stores); others take
     // the general loop.  Both add the slots in slot order.
     constexpr int SC = wbp_bwd_slots<NLOG, RHO>();
-    const bool full = S == SC && frame0 + SC <= a.F;
-    auto flush_all = [&](int it, bool lastit) {
-        float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
-        if (full) {
-            for (int i4 = tid; i4 < n * 2 * N / 4; i4 += blockDim.x) {
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (!(lastit && (((4 * i4) / N) & 1))) {
+    for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+        const bool first = bt == (int64_t)blockIdx.x;  // the partial's first batch stores
+        const int64_t frame0 = bt * S, frame = frame0 + slot;
+        const bool active = frame < a.F;
+        const bool full = S == SC && frame0 + SC <= a.F;
+        sfor<0, G>([&](auto g) {
+            sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
+            sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+        });
+        // store into the partial (its first batch) or add to it
+        auto put4 = [&](float *p, float4 v) {
+            if (!first) {
+                const float4 o = *reinterpret_cast<const float4 *>(p);
+                v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+            }
+            *reinterpret_cast<float4 *>(p) = v;
+        };
+        auto put1 = [&](float *p, float v) { *p = first ? v : *p + v; };
+        auto flush_all = [&](int it, bool lastit) {
+            float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+            if (full) {
+                for (int i4 = tid; i4 < n * 2 * N / 4; i4 += blockDim.x) {
+                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (!(lastit && (((4 * i4) / N) & 1))) {
+                        sfor<0, SC>([&](auto sc) {
+                            const float4 w = *reinterpret_cast<const float4 *>(smem + (size_t)sc * PS + 4 * N + 4 * i4);
+                            v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+                        });
+                    }
+                    put4(part + 4 * i4, v);
+                }
+                return;
+            }
+            for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
+                float v = 0.f;
+                if (!(lastit && ((idx / N) & 1)))
+                    for (int s = 0; s < S; ++s)
+                        if (frame0 + s < a.F) v += smem[(size_t)s * PS + 4 * N + idx];
+                put1(part + idx, v);
+            }
+        };
+        auto flush = [&](auto gc, int d, int par, int it) {
+            constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
+            float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N + lo * 2 * N;
+            const float *w0 = smem + 4 * N + par * RHO * N;
+            if (full) {
+                for (int i4 = tid; i4 < r * N / 4; i4 += blockDim.x) {
+                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                     sfor<0, SC>([&](auto sc) {
-                        const float4 w = *reinterpret_cast<const float4 *>(smem + (size_t)sc * PS + 4 * N + 4 * i4);
+                        const float4 w = *reinterpret_cast<const float4 *>(w0 + (size_t)sc * PS + 4 * i4);
                         v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
                     });
+                    const int idx = 4 * i4;
+                    put4(part + ((idx / N) * 2 + d) * N + (idx & (N - 1)), v);
                 }
-                *reinterpret_cast<float4 *>(part + 4 * i4) = v;
+                return;
             }
-            return;
-        }
-        for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
-            float v = 0.f;
-            if (!(lastit && ((idx / N) & 1)))
+            for (int idx = tid; idx < r * N; idx += blockDim.x) {
+                float v = 0.f;
                 for (int s = 0; s < S; ++s)
-                    if (frame0 + s < a.F) v += smem[(size_t)s * PS + 4 * N + idx];
-            part[idx] = v;
-        }
-    };
-    auto flush = [&](auto gc, int d, int par, int it) {
-        constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
-        float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N + lo * 2 * N;
-        const float *w0 = smem + 4 * N + par * RHO * N;
-        if (full) {
-            for (int i4 = tid; i4 < r * N / 4; i4 += blockDim.x) {
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                sfor<0, SC>([&](auto sc) {
-                    const float4 w = *reinterpret_cast<const float4 *>(w0 + (size_t)sc * PS + 4 * i4);
-                    v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
-                });
-                const int idx = 4 * i4;
-                *reinterpret_cast<float4 *>(part + ((idx / N) * 2 + d) * N + (idx & (N - 1))) = v;
+                    if (frame0 + s < a.F) v += w0[(size_t)s * PS + idx];
+                put1(part + ((idx / N) * 2 + d) * N + (idx & (N - 1)), v);
             }
-            return;
-        }
-        for (int idx = tid; idx < r * N; idx += blockDim.x) {
-            float v = 0.f;
-            for (int s = 0; s < S; ++s)
-                if (frame0 + s < a.F) v += w0[(size_t)s * PS + idx];
-            part[((idx / N) * 2 + d) * N + (idx & (N - 1))] = v;
-        }
-    };
+        };
 
-    for (int it = a.T - 1; it >= 0; --it) {
-        const int q = order_at(it);
-        const float *wt = a.w + (int64_t)it * n * 2 * N;
-        const bool lastit = (it == a.T - 1);
-        if (active) {
-            const int8_t *e = ords + q * 16;
-            const int base = GMap<P, G - 1>::base(t);
-            frozen_bits = 0;
-            sfor<0, ROWS>([&](auto i) {
-                const int p = base + GMap<P, G - 1>::off(i);
-                const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
-                toprow[i] = j;
-                frozen_bits |= (a.meta[j] == -2 ? 1u : 0u) << i;
-            });
-            if constexpr (MAPPED) {
-                const int bb = GMap<P, GB>::base(t);
-                sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
-            }
-            const float *src = a.llr + frame * N;
-            const int b0 = GMap<P, 0>::base(t);
-            if constexpr (KP == NLOG) {
-                sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[relabel_to_row(b0 + GMap<P, 0>::off(i), e, n, 0)]; });
-            } else {
-                sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[b0 + GMap<P, 0>::off(i)]; });
-            }
-            // entering R state
-            if (it == 0) {
-                RState<P>::each(st, t, [&](float &v, int64_t) { v = 0.f; });
-            } else {
-                const float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS;
-                RState<P>::each(st, t, [&](float &v, int64_t o) { v = ck[o]; });
-            }
-            // a trellis switch after this iteration reset the inner levels of
-            // the permuted range: nothing flows back through them
-            if constexpr (KP > 0) {
-                if (!lastit && order_at(it + 1) != q) {
-                    sfor<GB, G>([&](auto g) {
-                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
-                        if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+        for (int it = a.T - 1; it >= 0; --it) {
+            const int q = order_at(it);
+            const float *wt = a.w + (int64_t)it * n * 2 * N;
+            const bool lastit = (it == a.T - 1);
+            if (active) {
+                const int8_t *e = ords + q * 16;
+                const int base = GMap<P, G - 1>::base(t);
+                frozen_bits = 0;
+                sfor<0, ROWS>([&](auto i) {
+                    const int p = base + GMap<P, G - 1>::off(i);
+                    const int j = (KP > 0) ? relabel_to_row(p, e, n, LOWBITS) : p;
+                    toprow[i] = j;
+                    frozen_bits |= (a.meta[j] == -2 ? 1u : 0u) << i;
+                });
+                if constexpr (MAPPED) {
+                    const int bb = GMap<P, GB>::base(t);
+                    sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
+                }
+                const float *src = a.llr + frame * N;
+                const int b0 = GMap<P, 0>::base(t);
+                if constexpr (KP == NLOG) {
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[relabel_to_row(b0 + GMap<P, 0>::off(i), e, n, 0)]; });
+                } else {
+                    sfor<0, ROWS>([&](auto i) { st.Lbot[0][i] = src[b0 + GMap<P, 0>::off(i)]; });
+                }
+                // entering R state
+                if (it == 0) {
+                    RState<P>::each(st, t, [&](float &v, int64_t) { v = 0.f; });
+                } else {
+                    const float *ck = a.ckpt + ((frame * (a.T - 1) + (it - 1)) * (int64_t)NREG) * TPS;
+                    RState<P>::each(st, t, [&](float &v, int64_t o) { v = ck[o]; });
+                }
+                // a trellis switch after this iteration reset the inner levels of
+                // the permuted range: nothing flows back through them
+                if constexpr (KP > 0) {
+                    if (!lastit && order_at(it + 1) != q) {
+                        sfor<GB, G>([&](auto g) {
+                            sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gsi[g][l][i] = 0.f; }); });
+                            if constexpr (g < G - 1) sfor<0, ROWS>([&](auto i) { gst[g][i] = 0.f; });
+                        });
+                    }
+                }
+                // the reverse R sweep writes the L adjoints; without it (the last
+                // iteration) they start at zero
+                if (lastit) {
+                    sfor<0, G>([&](auto g) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[g][l][i] = 0.f; }); });
+                        sfor<0, ROWS>([&](auto i) { glb[g][i] = 0.f; });
                     });
                 }
             }
-            // the reverse R sweep writes the L adjoints; without it (the last
-            // iteration) they start at zero
-            if (lastit) {
+            // ---- recompute the L sweep ----
+            sfor<0, G - 1>([&](auto g) {
+                if (active) {
+                    const int base = GMap<P, g>::base(t);
+                    if constexpr (g > 0) {
+                        const float *lb = buf + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
+                        else sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+                    }
+                    float out[ROWS];
+                    wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
+                    float *lt = buf + ((g + 1) & 1) * N;
+                    sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
+                }
+                boundary_sync<WAVE>();
+            });
+            float prior[ROWS];
+            sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
+            if (active) {
+                const int base = GMap<P, G - 1>::base(t);
+                if constexpr (G > 1) {
+                    const float *lb = buf + ((G - 1) & 1) * N;
+                    if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+                    else sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
+                }
+                wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
+                // ---- recompute the R sweep, keeping every level ----
+                if (!lastit) {
+                    sfor<0, ROWS>([&](auto i) { Rtsw[G - 1][i] = prior[i]; });
+                    float rb[ROWS];
+                    wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], Rsw[G - 1], prior, rb, wt + base);
+                    if constexpr (G > 1) {
+                        float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                        if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                        else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
+                    }
+                }
+            }
+            boundary_sync<WAVE>();
+            if (!lastit) {
+                sfor<0, G - 1>([&](auto k) {
+                    constexpr int g = G - 2 - k;
+                    if (active) {
+                        const int base = GMap<P, g>::base(t);
+                        const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
+                        sfor<0, ROWS>([&](auto i) { Rtsw[g][i] = rs[base + GMap<P, g>::off(i)]; });
+                        float rb[ROWS];
+                        wgroup_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], rb, wt + base);
+                        if constexpr (g > 0) {
+                            float *rt = buf + 2 * N + (g & 1) * N;
+                            if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                            else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                        }
+                    }
+                    boundary_sync<WAVE>();
+                });
+                // ---- reverse of the R sweep: groups bottom to top ----
                 sfor<0, G>([&](auto g) {
-                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[g][l][i] = 0.f; }); });
-                    sfor<0, ROWS>([&](auto i) { glb[g][i] = 0.f; });
+                    if constexpr (g > 0 && !WAVE) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
+                    if (active) {
+                        const int base = GMap<P, g>::base(t);
+                        float gb[ROWS];
+                        if constexpr (g == 0) {
+                            sfor<0, ROWS>([&](auto i) { gb[i] = 0.f; });
+                        } else {
+                            const float *src = buf + (g & 1) * N;
+                            if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { gb[i] = src[baddr[i]]; });
+                            else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
+                        }
+                        float gtop[ROWS];
+                        // staged at [sl][row] of this step, or at [stage][1][row] for one-wave frames
+                        float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2 + 1) * N + base
+                                                : buf + 4 * N + (g & 1) * RHO * N + base;
+                        constexpr int SLS = WAVE ? 2 * N : N;
+                        rev_group_R<P, g, g == 0>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
+                                          wt + base, [&](int sl, int off, float v) { gws[sl * SLS + off] = v; });
+                        if constexpr (g < G - 1) {
+                            float *dst = buf + ((g + 1) & 1) * N;
+                            sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
+                        }
+                    }
+                    boundary_sync<WAVE>();
                 });
             }
-        }
-        // ---- recompute the L sweep ----
-        sfor<0, G - 1>([&](auto g) {
-            if (active) {
-                const int base = GMap<P, g>::base(t);
-                if constexpr (g > 0) {
-                    const float *lb = buf + (g & 1) * N;
-                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[baddr[i]]; });
-                    else sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
+            // ---- reverse of the L sweep: groups top to bottom (it writes the new
+            // state adjoint, every entry the reverse R sweep reads) ----
+            const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
+            sfor<0, G>([&](auto k) {
+                constexpr int g = G - 1 - k;
+                if constexpr (!WAVE) {
+                    if constexpr (k == 0) {
+                        if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
+                    } else {
+                        flush(std::integral_constant<int, g + 1>{}, 0, (step0 + k - 1) & 1, it);
+                    }
                 }
-                float out[ROWS];
-                wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
-                float *lt = buf + ((g + 1) & 1) * N;
-                sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
-            }
-            boundary_sync<WAVE>();
-        });
-        float prior[ROWS];
-        sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
-        if (active) {
-            const int base = GMap<P, G - 1>::base(t);
-            if constexpr (G > 1) {
-                const float *lb = buf + ((G - 1) & 1) * N;
-                if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
-                else sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
-            }
-            wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
-            // ---- recompute the R sweep, keeping every level ----
-            if (!lastit) {
-                sfor<0, ROWS>([&](auto i) { Rtsw[G - 1][i] = prior[i]; });
-                float rb[ROWS];
-                wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], Rsw[G - 1], prior, rb, wt + base);
-                if constexpr (G > 1) {
-                    float *rt = buf + 2 * N + ((G - 1) & 1) * N;
-                    if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
-                    else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
-                }
-            }
-        }
-        boundary_sync<WAVE>();
-        if (!lastit) {
-            sfor<0, G - 1>([&](auto k) {
-                constexpr int g = G - 2 - k;
+                float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2) * N : buf + 4 * N + ((step0 + k) & 1) * RHO * N;
+                constexpr int SLS = WAVE ? 2 * N : N;
                 if (active) {
                     const int base = GMap<P, g>::base(t);
-                    const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
-                    sfor<0, ROWS>([&](auto i) { Rtsw[g][i] = rs[base + GMap<P, g>::off(i)]; });
-                    float rb[ROWS];
-                    wgroup_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], rb, wt + base);
+                    float gt[ROWS];
+                    auto sink = [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; };
+                    if constexpr (g == G - 1) {
+                        // the output adjoint enters at the last iteration only
+                        if (lastit) {
+                            sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
+                            rev_group_L<P, g, true, false>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
+                                                           gsi[g], gst[g], wt + base, sink);
+                        } else {
+                            rev_group_L<P, g, true, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
+                                                          gsi[g], gst[g], wt + base, sink);
+                        }
+                    } else {
+                        const float *src = buf + 2 * N + ((g + 1) & 1) * N;
+                        sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
+                        rev_group_L<P, g, false, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g],
+                                                        glb[g], gsi[g], gst[g], wt + base, sink);
+                    }
                     if constexpr (g > 0) {
-                        float *rt = buf + 2 * N + (g & 1) * N;
-                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
-                        else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, g>::off(i)] = rb[i]; });
+                        float *dst = buf + 2 * N + (g & 1) * N;
+                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { dst[baddr[i]] = glb[g][i]; });
+                        else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[g][i]; });
                     }
                 }
                 boundary_sync<WAVE>();
             });
-            // ---- reverse of the R sweep: groups bottom to top ----
-            sfor<0, G>([&](auto g) {
-                if constexpr (g > 0 && !WAVE) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
-                if (active) {
-                    const int base = GMap<P, g>::base(t);
-                    float gb[ROWS];
-                    if constexpr (g == 0) {
-                        sfor<0, ROWS>([&](auto i) { gb[i] = 0.f; });
-                    } else {
-                        const float *src = buf + (g & 1) * N;
-                        if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { gb[i] = src[baddr[i]]; });
-                        else sfor<0, ROWS>([&](auto i) { gb[i] = src[base + GMap<P, g>::off(i)]; });
-                    }
-                    float gtop[ROWS];
-                    // staged at [sl][row] of this step, or at [stage][1][row] for one-wave frames
-                    float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2 + 1) * N + base
-                                            : buf + 4 * N + (g & 1) * RHO * N + base;
-                    constexpr int SLS = WAVE ? 2 * N : N;
-                    rev_group_R<P, g, g == 0>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                      wt + base, [&](int sl, int off, float v) { gws[sl * SLS + off] = v; });
-                    if constexpr (g < G - 1) {
-                        float *dst = buf + ((g + 1) & 1) * N;
-                        sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
-                    }
-                }
-                boundary_sync<WAVE>();
-            });
-        }
-        // ---- reverse of the L sweep: groups top to bottom (it writes the new
-        // state adjoint, every entry the reverse R sweep reads) ----
-        const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
-        sfor<0, G>([&](auto k) {
-            constexpr int g = G - 1 - k;
-            if constexpr (!WAVE) {
-                if constexpr (k == 0) {
-                    if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
-                } else {
-                    flush(std::integral_constant<int, g + 1>{}, 0, (step0 + k - 1) & 1, it);
+            if constexpr (WAVE) {
+                __syncthreads();
+                flush_all(it, lastit);
+            } else {
+                flush(std::integral_constant<int, 0>{}, 0, (step0 + G - 1) & 1, it);
+                if (lastit && first) {
+                    // the last iteration runs no R sweep: its R weights get no gradient
+                    float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+                    for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
                 }
             }
-            float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2) * N : buf + 4 * N + ((step0 + k) & 1) * RHO * N;
-            constexpr int SLS = WAVE ? 2 * N : N;
-            if (active) {
-                const int base = GMap<P, g>::base(t);
-                float gt[ROWS];
-                auto sink = [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; };
-                if constexpr (g == G - 1) {
-                    // the output adjoint enters at the last iteration only
-                    if (lastit) {
-                        sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
-                        rev_group_L<P, g, true, false>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
-                                                       gsi[g], gst[g], wt + base, sink);
-                    } else {
-                        rev_group_L<P, g, true, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
-                                                      gsi[g], gst[g], wt + base, sink);
-                    }
-                } else {
-                    const float *src = buf + 2 * N + ((g + 1) & 1) * N;
-                    sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
-                    rev_group_L<P, g, false, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g],
-                                                    glb[g], gsi[g], gst[g], wt + base, sink);
-                }
-                if constexpr (g > 0) {
-                    float *dst = buf + 2 * N + (g & 1) * N;
-                    if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { dst[baddr[i]] = glb[g][i]; });
-                    else sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = glb[g][i]; });
-                }
-            }
-            boundary_sync<WAVE>();
-        });
-        if constexpr (WAVE) {
             __syncthreads();
-            flush_all(it, lastit);
-        } else {
-            flush(std::integral_constant<int, 0>{}, 0, (step0 + G - 1) & 1, it);
-            if (lastit) {
-                // the last iteration runs no R sweep: its R weights get no gradient
-                float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
-                for (int idx = tid; idx < n * N; idx += blockDim.x) part[((idx / N) * 2 + 1) * N + (idx & (N - 1))] = 0.f;
-            }
         }
-        __syncthreads();
     }
 }
 

@@ -208,9 +208,13 @@ def test_weighted_large_frames_more_than_the_grid(orc, pbp):
     assert np.array_equal(gw.view(np.uint32), again.view(np.uint32))
 
 
-@pytest.mark.parametrize("N,K,T,F", [(64, 32, 3, 16 * 70 + 5), (16, 8, 2, 64 * 65 + 3)])
+@pytest.mark.parametrize("N,K,T,F", [(64, 32, 3, 32 * 300 + 5), (16, 8, 2, 128 * 270 + 3),
+                                     (256, 144, 3, 8 * 300 + 3), (1024, 512, 2, 600)])
 def test_weighted_gradient_over_many_workgroups(orc, pbp, N, K, T, F):
-    # more than 64 workgroup partials: both levels of the gradient reduction
+    # more batches of frames than the adjoint's fixed grid (256 workgroups up
+    # to N = 256, 512 above): the first workgroups take a second batch and add
+    # into their partial, the last batch is ragged, and more than 64 partials
+    # take both levels of the gradient reduction
     n = N.bit_length() - 1
     oc, u, llr = _setup(orc, N, K, F, seed=3 + F)
     rng = np.random.default_rng(F)
