@@ -46,7 +46,8 @@ int run_wbp(const WbpLaunch &L) {
     if (lds > 160 * 1024) return fail(PC_EINVAL, "LDS budget exceeded for weighted BP");
     if (L.backward) {
         if constexpr (NLOG >= kWbpBigLog) {
-            const size_t big_lds = WbpLds<P, false>::bytes(1);
+            constexpr size_t big_lds = BigLds<P>::bytes;
+            static_assert(big_lds <= 160 * 1024, "large-frame adjoint exceeds the LDS");
             hipLaunchKernelGGL((k_wbp_bwd_big<NLOG, KP>), dim3(L.grid), dim3(P::TPS), big_lds, L.stream, L.args);
         } else {
             hipLaunchKernelGGL((k_wbp_bwd<NLOG, KP, 2>), dim3(L.grid), dim3(S * P::TPS), lds, L.stream, L.args);

@@ -782,6 +782,22 @@ struct BigScratch {
     static constexpr size_t per_wg_floats = 4 * ASZ;                  // [array][group][thread][GE]
 };
 
+// LDS of the large-frame adjoint: the four boundary buffers (4N floats) and,
+// for its first LG groups, the L messages that three later phases read back
+// (the one array read three times), as [group][value][thread] so that a
+// wave's accesses fall on consecutive banks; the other groups' L messages
+// stay in the scratch.  LG fills the workgroup's share of the LDS: all of it
+// at N = 4096 (one workgroup per CU), half at N = 2048 (two per CU).
+template <class P>
+struct BigLds {
+    static constexpr int GE = BigScratch<P>::GE;
+    static constexpr size_t budget = (size_t)(P::N >= 4096 ? 160 : 80) * 1024;
+    static constexpr size_t base_bytes = 4 * (size_t)P::N * sizeof(float);
+    static constexpr int LG0 = (int)((budget - base_bytes) / ((size_t)GE * P::TPS * sizeof(float)));
+    static constexpr int LG = LG0 < P::G ? LG0 : P::G;
+    static constexpr size_t bytes = base_bytes + (size_t)LG * GE * P::TPS * sizeof(float);
+};
+
 template <int NLOG, int KP>
 __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
     using P = Plan<NLOG, KP, 2>;
@@ -792,11 +808,11 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
     constexpr int GE = BigScratch<P>::GE;
     constexpr size_t ASZ = BigScratch<P>::ASZ;
     const int t = threadIdx.x;
+    constexpr int LG = BigLds<P>::LG;
     extern __shared__ __align__(16) float smem[];
-    float *const buf = smem;  // [A0 A1 | B0 B1]
-    int8_t *const ords = reinterpret_cast<int8_t *>(smem + 4 * N);
-    for (int i = t; i < 8 * 16; i += blockDim.x) ords[i] = a.orders[i >> 4][i & 15];
-    __syncthreads();
+    float *const buf = smem;        // [A0 A1 | B0 B1]
+    float *const lsl = smem + 4 * N;  // L messages of groups 0..LG-1
+    const int8_t *const ords = &a.orders[0][0];
 
     float *const scr = a.scratch + (size_t)blockIdx.x * BigScratch<P>::per_wg_floats;
     // scratch arrays: L messages, R sweep messages, adjoint of the R state,
@@ -863,12 +879,32 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
             };
             auto load2 = [&](int arr, auto gc, float (&x)[RI][ROWS], float (&y)[ROWS]) {
                 constexpr int g = decltype(gc)::value;
+                if constexpr (g < LG) {
+                    if (arr == LS) {
+                        const float *b = lsl + (size_t)g * GE * TPS + t;
+                        sfor<0, P::size(g) - 1>([&](auto l) {
+                            sfor<0, ROWS>([&](auto i) { x[l][i] = b[(l * ROWS + i) * TPS]; });
+                        });
+                        sfor<0, ROWS>([&](auto i) { y[i] = b[(RI * ROWS + i) * TPS]; });
+                        return;
+                    }
+                }
                 const float *b = blk(arr, g, tid_here());
                 sfor<0, P::size(g) - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { x[l][i] = b[l * ROWS + i]; }); });
                 sfor<0, ROWS>([&](auto i) { y[i] = b[RI * ROWS + i]; });
             };
             auto store2 = [&](int arr, auto gc, const float (&x)[RI][ROWS], const float (&y)[ROWS]) {
                 constexpr int g = decltype(gc)::value;
+                if constexpr (g < LG) {
+                    if (arr == LS) {
+                        float *b = lsl + (size_t)g * GE * TPS + t;
+                        sfor<0, P::size(g) - 1>([&](auto l) {
+                            sfor<0, ROWS>([&](auto i) { b[(l * ROWS + i) * TPS] = x[l][i]; });
+                        });
+                        sfor<0, ROWS>([&](auto i) { b[(RI * ROWS + i) * TPS] = y[i]; });
+                        return;
+                    }
+                }
                 float *b = blk(arr, g, tid_here());
                 sfor<0, P::size(g) - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { b[l * ROWS + i] = x[l][i]; }); });
                 sfor<0, ROWS>([&](auto i) { b[RI * ROWS + i] = y[i]; });
