@@ -910,6 +910,14 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                 sfor<0, ROWS>([&](auto i) { b[RI * ROWS + i] = y[i]; });
             };
 
+            // Arrays that one phase's last group hands to the next phase's
+            // first (the same group) stay in registers across the barrier:
+            // the last group's L messages (recompute L -> recompute R), group
+            // 0's R sweep messages (recompute R -> reverse R), the last group's
+            // L adjoints (reverse R -> reverse L)
+            float hl_lint[RI][ROWS], hl_lbot[ROWS];
+            float h0_rsw[RI][ROWS], h0_rtop[ROWS];
+            float hg_gli[RI][ROWS], hg_glb[ROWS];
             // ---- recompute the L sweep (groups 0..G-1) ----
             sfor<0, G>([&](auto g) {
                 const int base = GMap<P, g>::base(t);
@@ -925,6 +933,10 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                 load_state(g, rint, rtop);
                 wgroup_L<P, g>(lbot, lint, rint, rtop, out, wt + base);
                 store2(LS, g, lint, lbot);
+                if constexpr (g == G - 1) {
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { hl_lint[l][i] = lint[l][i]; }); });
+                    sfor<0, ROWS>([&](auto i) { hl_lbot[i] = lbot[i]; });
+                }
                 if constexpr (g < G - 1) {
                     float *lt = buf + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
@@ -937,7 +949,12 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     constexpr int g = G - 1 - k;
                     const int base = GMap<P, g>::base(t);
                     float lbot[ROWS], lint[RI][ROWS], rsw[RI][ROWS], rtop[ROWS], rb[ROWS];
-                    load2(LS, std::integral_constant<int, g>{}, lint, lbot);
+                    if constexpr (g == G - 1) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { lint[l][i] = hl_lint[l][i]; }); });
+                        sfor<0, ROWS>([&](auto i) { lbot[i] = hl_lbot[i]; });
+                    } else {
+                        load2(LS, std::integral_constant<int, g>{}, lint, lbot);
+                    }
                     if constexpr (g == G - 1) {
                         sfor<0, ROWS>([&](auto i) { rtop[i] = prior[i]; });
                     } else {
@@ -945,7 +962,12 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                         sfor<0, ROWS>([&](auto i) { rtop[i] = rs[base + GMap<P, g>::off(i)]; });
                     }
                     wgroup_R<P, g>(lbot, lint, rsw, rtop, rb, wt + base);
-                    store2(RS, std::integral_constant<int, g>{}, rsw, rtop);
+                    if constexpr (g == 0) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { h0_rsw[l][i] = rsw[l][i]; }); });
+                        sfor<0, ROWS>([&](auto i) { h0_rtop[i] = rtop[i]; });
+                    } else {
+                        store2(RS, std::integral_constant<int, g>{}, rsw, rtop);
+                    }
                     if constexpr (g > 0) {
                         float *rt = buf + 2 * N + (g & 1) * N;
                         if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
@@ -959,7 +981,12 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     float lbot[ROWS], lint[RI][ROWS], rsw[RI][ROWS], rtsw[ROWS], gsi[RI][ROWS], gst[ROWS];
                     float gli[RI][ROWS], glb[ROWS], gb[ROWS], gtop[ROWS];
                     load2(LS, g, lint, lbot);
-                    load2(RS, g, rsw, rtsw);
+                    if constexpr (g == 0) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { rsw[l][i] = h0_rsw[l][i]; }); });
+                        sfor<0, ROWS>([&](auto i) { rtsw[i] = h0_rtop[i]; });
+                    } else {
+                        load2(RS, g, rsw, rtsw);
+                    }
                     // the adjoint of the R state leaving this iteration; a trellis
                     // switch after it reset the inner levels of the permuted range
                     load2(GS, g, gsi, gst);
@@ -980,7 +1007,12 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
                     rev_group_R<P, g, g == 0>(lbot, lint, rsw, rtsw, gb, gsi, gli, glb, gtop, wt + base,
                                       sink(P::lo(g), 1, base));
-                    store2(GL, g, gli, glb);
+                    if constexpr (g == G - 1) {
+                        sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { hg_gli[l][i] = gli[l][i]; }); });
+                        sfor<0, ROWS>([&](auto i) { hg_glb[i] = glb[i]; });
+                    } else {
+                        store2(GL, g, gli, glb);
+                    }
                     if constexpr (g < G - 1) {
                         float *dst = buf + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[i]; });
@@ -1004,6 +1036,9 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                 if (lastit) {
                     sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = 0.f; }); });
                     sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
+                } else if constexpr (g == G - 1) {
+                    sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = hg_gli[l][i]; }); });
+                    sfor<0, ROWS>([&](auto i) { glb[i] = hg_glb[i]; });
                 } else {
                     load2(GL, std::integral_constant<int, g>{}, gli, glb);
                 }
