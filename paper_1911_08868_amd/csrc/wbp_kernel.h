@@ -23,9 +23,11 @@
 // dg/dx = sgn(y), else dg/dy = sgn(x) (ties route to the first argument).
 // Each reverse step stages the weight gradients of its group per frame in LDS;
 // the next step (after the barrier that ends this one) sums them over the
-// workgroup's frames in slot order and writes them as this workgroup's
-// partial.  A two-level reduction then sums the partials in workgroup order,
-// so the result does not depend on scheduling.
+// workgroup's frames in slot order and adds them into this workgroup's
+// partial.  The adjoint's grid is fixed; each workgroup walks its batches of
+// frames in order, the first storing the partial and the rest adding to it.
+// A two-level reduction then sums the partials in workgroup order, so the
+// result does not depend on scheduling or on the device.
 #pragma once
 
 #include "bp_core.h"
@@ -494,15 +496,14 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     int baddr[ROWS], toprow[ROWS];
     uint32_t frozen_bits = 0;
     auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
-    // Sum the weight gradients that one reverse step (group g, sweep d)
-    // staged in W[par] over the workgroup's frames, in slot order, and store
-    // them as this workgroup's partial of iteration it.
-    // one-wave frames: sum the iteration's staged gradients over the
-    // workgroup's frames, in slot order (the last iteration's R weights get 0)
-    // A workgroup launched with the usual slot count whose slots all hold
-    // frames sums its slots in a fixed unrolled order, four consecutive
-    // entries per thread (16-byte LDS reads and global stores); others take
-    // the general loop.  Both add the slots in slot order.
+    // flush: sum the weight gradients that one reverse step (group g, sweep
+    // d) staged in W[par] over the batch's frames, in slot order, and add
+    // them into this workgroup's partial of iteration it.  flush_all (one-wave
+    // frames): the same for the whole iteration's staged gradients (the last
+    // iteration's R weights get 0).  A batch whose slots all hold frames
+    // sums its slots in a fixed unrolled order, four consecutive entries per
+    // thread (16-byte LDS reads and global accesses); others take the general
+    // loop.  Both add the slots in slot order.
     constexpr int SC = wbp_bwd_slots<NLOG, RHO>();
     for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
         const bool first = bt == (int64_t)blockIdx.x;  // the partial's first batch stores
