@@ -118,25 +118,6 @@ __device__ __forceinline__ int thread_of(int e, int s) {
     }
 }
 
-// The lane bit that carries element bit k at stage s under thread_of (6 and
-// up: a wave bit, or no lane at all).
-template <int W>
-constexpr int lane_bit_of(int k, int s) {
-    if (W == 0) return k;
-    if (s <= 6) return k <= 4 ? k + 1 : k == 5 ? 0 : 6;
-    return k <= 2 ? k : (k >= 6 && k < 6 + W) ? 3 + (k - 6) : 3 + W + (k - 3);
-}
-
-// The butterfly over lane bit K taken only by the threads with sel (the
-// others keep their pair; every lane of the wave takes part in the moves).
-template <int K>
-__device__ __forceinline__ void bfly_sel(float &top, float &bot, int lane, bool sel) {
-    float c0 = top, c1 = bot;
-    bfly_wave<K>(c0, c1, lane);
-    top = sel ? c0 : top;
-    bot = sel ? c1 : bot;
-}
-
 // Bank swizzle of the exchange slots: bits 7, 8, 9 of a slot index (the
 // thread's bits 6, 7, 8) are xor-ed into bits 0, 1, 5, so that the
 // transposition between stages 6 and 7 reads (and, backwards, writes) 64
@@ -212,17 +193,10 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 6) k_alg1o(Alg1Args a
     // A block of two stages (rho_range = 2) swaps bits rl-1 and rl, which in a
     // thread's pair is the butterfly on element bit rl-1 (element bit and slot
     // trade places).  Where that element bit sits on a lane bit, the block's
-    // boundaries take that butterfly on the block's threads in place of the
-    // exchange through LDS; at the stage that meets a boundary that lane bit
-    // is known at compile time (A after stage s = rl-1 carries element bit s,
-    // B at stage s = m element bit s-2), so the move is a DPP or lane-row
-    // swap.  Per stage s, two bits at 2 s say what a marked L transition after
-    // stage s (lact) or R transition from stage s (ract) does: 1 the move into
-    // the block's coordinates, 2 the move out of them, 3 the exchange through
-    // LDS (A or B by the stage).  fsel_lo / fsel_hi: the thread's element is
-    // in the block (at stages 1..6 / 7..n), so it takes the fast moves.
-    uint32_t lact = 0u, ract = 0u;
-    bool fsel_lo = false, fsel_hi = false;
+    // boundaries take that butterfly on the block's threads (fast: bit 0 A,
+    // bit 1 B; lane bits kA, kB) in place of the exchange through LDS.
+    uint32_t fast = 0u;
+    int kA = 0, kB = 0;
     // alternating buffer of the exchanges with a barrier
     int xsel = 0;
     auto slot = [&](int b, int j) -> int {
@@ -242,6 +216,28 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 6) k_alg1o(Alg1Args a
     // stage m+1 hold one row of each.  Every other thread keeps its butterfly.
     auto in_a = [&](int e) -> bool { return (e >> (m - 1)) == blk; };
     auto in_b = [&](int e) -> bool { return (e >> m) == (blk >> 1); };
+    // the lane bit that carries element bit k at stage s (6 and up: a wave bit)
+    auto lane_bit = [&](int k, int s) -> int {
+        if constexpr (W == 0) {
+            return k;
+        } else if (s <= 6) {
+            return k <= 4 ? k + 1 : k == 5 ? 0 : 6;
+        } else {
+            return k <= 2 ? k : (k >= 6 && k < 6 + W) ? 3 + (k - 6) : 3 + W + (k - 3);
+        }
+    };
+    // the butterfly on lane bit k (uniform), kept by the threads with sel; the
+    // partner's value comes by ds_bpermute (one code path for every k)
+    auto conv = [&](float &v0, float &v1, int k, bool sel) {
+        const bool b = (lane >> k) & 1;
+        const int recv = __builtin_amdgcn_ds_bpermute((lane ^ (1 << k)) << 2, __float_as_int(b ? v0 : v1));
+        if (sel) {
+            if (b)
+                v0 = __int_as_float(recv);
+            else
+                v1 = __int_as_float(recv);
+        }
+    };
     // the exchange slots and masks for the current block (the C slots again
     // only if redo_c); the barrier needs are published as wave flags in
     // misc[32 + w] (read after the caller's next barrier)
@@ -250,26 +246,20 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 6) k_alg1o(Alg1Args a
         bool ca = false, cb = false;
         const bool hasA = m > 0 && rl >= 2 && !(W > 0 && rl - 1 == 6);
         const bool hasB = m > 0 && m < n && !(W > 0 && m == 6);
-        uint32_t fast = 0u;  // bit 0: A takes the fast move, bit 1: B
+        fast = 0u;
         if (rr == 2) {
-            const int kA = lane_bit_of<W>(rl - 1, rl), kB = lane_bit_of<W>(rl - 1, m);
+            kA = lane_bit(rl - 1, rl);
+            kB = lane_bit(rl - 1, m);
             fast = (hasA && kA < 6 ? 1u : 0u) | (hasB && kB < 6 ? 2u : 0u);
         }
-        lact = ract = 0u;
         if (hasA) {
             lmask |= 1u << (rl - 1);
             rmask |= 1u << rl;
-            lact |= ((fast & 1u) ? 1u : 3u) << (2 * (rl - 1));
-            ract |= ((fast & 1u) ? 2u : 3u) << (2 * rl);
         }
         if (hasB) {
             lmask |= 1u << m;
             rmask |= 1u << (m + 1);
-            lact |= ((fast & 2u) ? 2u : 3u) << (2 * m);
-            ract |= ((fast & 2u) ? 1u : 3u) << (2 * (m + 1));
         }
-        fsel_lo = m > 0 && in_a(eL);
-        fsel_hi = m > 0 && in_a(eH);
         if (pe) {
             if constexpr (W > 0)
                 if (redo_c) cS = slots(6);
@@ -417,30 +407,23 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 6) k_alg1o(Alg1Args a
                         // they had (the butterfly undone on copies: it is an
                         // involution) through LDS instead
                         constexpr int K = W == 0 ? s - 1 : s >= 7 ? s - 4 : s;
-                        constexpr int KA = lane_bit_of<W>(s, s + 1);
-                        constexpr int KB = s >= 2 ? lane_bit_of<W>(s - 2, s) : 6;
                         bfly_wave<K>(lt, lb, lane);
                         if (__builtin_expect((lmask >> s) & 1u, 0)) {
-                            const uint32_t act = (lact >> (2 * s)) & 3u;
-                            const bool fsel = (W > 0 && s >= 7) ? fsel_hi : fsel_lo;
-                            if (act == 1u) {
-                                // into a two-stage block's coordinates
-                                if constexpr (KA < 6) bfly_sel<KA>(lt, lb, lane, fsel);
-                            } else if (act == 2u) {
-                                // out of a two-stage block: the butterfly undone,
-                                // back to row order, the butterfly again
-                                if constexpr (KB < 6) {
-                                    bfly_wave<K>(lt, lb, lane);
-                                    bfly_sel<KB>(lt, lb, lane, fsel);
-                                    bfly_wave<K>(lt, lb, lane);
-                                }
-                            } else {
-                                float u0 = lt, u1 = lb;
-                                bfly_wave<K>(u0, u1, lane);
-                                if (s == rl - 1)
-                                    exchange(lt, lb, u0, u1, aS, abar & 1u, false, pe && in_a(elem(s)));
+                            float u0 = lt, u1 = lb;
+                            bfly_wave<K>(u0, u1, lane);
+                            if (s == rl - 1) {
+                                if (fast & 1u)  // into a two-stage block's coordinates
+                                    conv(lt, lb, kA, in_a(elem(s)));
                                 else
-                                    exchange(lt, lb, u0, u1, bS, abar & 2u, false, pe && in_b(elem(s)));
+                                    exchange(lt, lb, u0, u1, aS, abar & 1u, false, pe && in_a(elem(s)));
+                            } else if (fast & 2u) {
+                                // out of a two-stage block: back to row order, then the butterfly
+                                conv(u0, u1, kB, in_a(elem(s)));
+                                lt = u0;
+                                lb = u1;
+                                bfly_wave<K>(lt, lb, lane);
+                            } else {
+                                exchange(lt, lb, u0, u1, bS, abar & 2u, false, pe && in_b(elem(s)));
                             }
                         }
                     }
@@ -501,30 +484,24 @@ __global__ void __launch_bounds__(Alg1OLds<NLOG>::threads, 6) k_alg1o(Alg1Args a
                     if (gather(frame, it) && can_stop) done = true;
                 } else {
                     constexpr int K = W == 0 ? s - 2 : s >= 8 ? s - 5 : s - 1;
-                    constexpr int KA = lane_bit_of<W>(s - 1, s);
-                    constexpr int KB = s >= 3 ? lane_bit_of<W>(s - 3, s - 1) : 6;
                     bfly_wave<K>(rt, rb, lane);
                     if (__builtin_expect((rmask >> s) & 1u, 0)) {
-                        const uint32_t act = (ract >> (2 * s)) & 3u;
-                        const bool fsel = (W > 0 && s >= 7) ? fsel_hi : fsel_lo;
-                        if (act == 2u) {
-                            // out of a two-stage block: the butterfly undone, back
-                            // to row order, the butterfly again
-                            if constexpr (KA < 6) {
+                        float u0 = rt, u1 = rb;
+                        bfly_wave<K>(u0, u1, lane);
+                        if (s == rl) {
+                            if (fast & 1u) {
+                                // out of a two-stage block: back to row order, then the butterfly
+                                conv(u0, u1, kA, in_a(elem(s)));
+                                rt = u0;
+                                rb = u1;
                                 bfly_wave<K>(rt, rb, lane);
-                                bfly_sel<KA>(rt, rb, lane, fsel);
-                                bfly_wave<K>(rt, rb, lane);
-                            }
-                        } else if (act == 1u) {
-                            // into a two-stage block's coordinates
-                            if constexpr (KB < 6) bfly_sel<KB>(rt, rb, lane, fsel);
-                        } else {
-                            float u0 = rt, u1 = rb;
-                            bfly_wave<K>(u0, u1, lane);
-                            if (s == rl)
+                            } else {
                                 exchange(rt, rb, u0, u1, aS, abar & 1u, true, pe && in_a(elem(s)));
-                            else
-                                exchange(rt, rb, u0, u1, bS, abar & 2u, true, pe && in_b(elem(s)));
+                            }
+                        } else if (fast & 2u) {
+                            conv(rt, rb, kB, in_a(elem(s)));  // into a two-stage block's coordinates
+                        } else {
+                            exchange(rt, rb, u0, u1, bS, abar & 2u, true, pe && in_b(elem(s)));
                         }
                     }
                 }
