@@ -191,20 +191,27 @@ def test_weighted_large_frames(orc, pbp, N, K, T, F, pp):
     assert np.all(gw[T - 1, :, 1] == 0.0)
 
 
-def test_weighted_large_frames_more_than_the_grid(orc, pbp):
-    # 260 frames on the 256-workgroup grid: four workgroups take a second
-    # frame and add into their partial
-    N, K, T, F = 4096, 2048, 2, 260
-    oc, u, llr = _setup(orc, N, K, F, seed=12)
+@pytest.mark.parametrize("N,K,T,F,pp", [(4096, 2048, 2, 260, None), (2048, 1100, 3, 515, (5, 1, 4))])
+def test_weighted_large_frames_more_than_the_grid(orc, pbp, N, K, T, F, pp):
+    # more frames than the fixed grid (256 workgroups at N = 4096, 512 at
+    # N = 2048): the first workgroups take a second frame and add into their
+    # partial; with the permuted range, the trellis changes at every iteration
+    n = N.bit_length() - 1
+    oc, u, llr = _setup(orc, N, K, F, seed=12 + N)
     rng = np.random.default_rng(12)
-    w = rng.uniform(0.8, 1.2, (T, 12, 2, N)).astype(np.float32).astype(np.float64)
+    w = rng.uniform(0.8, 1.2, (T, n, 2, N)).astype(np.float32).astype(np.float64)
     gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
-    out, gw = _gpu(pbp, oc, llr, w, T, None, gout)
-    opp = orc.WbpParams(fp32=True)
+    if pp:
+        k, tev, Q = pp
+        opp = orc.WbpParams(pp_mode=orc.PP_LASTK, k=k, T_ev=tev, Q=Q, seed=5, fp32=True)
+        gpp = pbp.PPParams(mode=pbp.PP_LASTK, k=k, period_T=tev, pool_Q=Q, seed=5)
+    else:
+        opp, gpp = orc.WbpParams(fp32=True), None
+    out, gw = _gpu(pbp, oc, llr, w, T, gpp, gout)
     assert np.array_equal(out.view(np.uint32), orc.wbp_forward(oc, llr, w, opp).astype(np.float32).view(np.uint32))
     ref_gw, _, absum = orc.wbp_backward(oc, llr, w, opp, gout, want_abs=True)
     _check_grad(gw, ref_gw, absum, F)
-    again = _gpu(pbp, oc, llr, w, T, None, gout)[1]
+    again = _gpu(pbp, oc, llr, w, T, gpp, gout)[1]
     assert np.array_equal(gw.view(np.uint32), again.view(np.uint32))
 
 
