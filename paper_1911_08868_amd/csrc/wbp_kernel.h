@@ -213,9 +213,9 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
 // the adjoints of the L messages it read into glint/glbot (every entry once),
 // returns in gtop the adjoint of the R message it read on its top level, and
 // stages the weight gradients of its stages (sweep 1) through
-// gw(stage - lo, row offset, value).  The derivative routing is the min-sum
-// rule of the forward's check function, written branch-free: a select per
-// route and the sign flips as bit operations.
+// gw(stage - lo, register, row offset, value).  The derivative routing is the
+// min-sum rule of the forward's check function, written branch-free: a select
+// per route and the sign flips as bit operations.
 template <class P, int g, bool ZBOT, class Sink>
 __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
@@ -229,7 +229,7 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
         if constexpr (ZBOT && sl == 0) {
             // a zero adjoint: zero weight gradients, nothing flows on
             sfor<0, ROWS>([&](auto i) {
-                gw(0, GMap<P, g>::off(i), 0.f);
+                gw(0, (int)i, GMap<P, g>::off(i), 0.f);
                 glbot[i] = 0.f;
                 if constexpr (r == 1) gtop[i] = 0.f;
             });
@@ -251,8 +251,8 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 // outputs: R'1 = w1 ms(r1, l2 + r2), R'2 = w2 ms(r1, l1) + r2
                 const float a = l2 + r2;
-                gw(sl, GMap<P, g>::off(i), go[i] * ms0c(a, r1));
-                gw(sl, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
+                gw(sl, (int)i, GMap<P, g>::off(i), go[i] * ms0c(a, r1));
+                gw(sl, ip, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 const bool c1 = __builtin_fabsf(r1) <= __builtin_fabsf(a);
                 const bool c2 = __builtin_fabsf(r1) <= __builtin_fabsf(l1);
@@ -275,7 +275,8 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
 // contributions) of its interior L messages.  Adds to glbot, writes the
 // adjoints of the entering R state it read into gsint/gstop (every entry
 // once; gstop untouched when the top level is the prior), stages the weight
-// gradients of its stages (sweep 0) through gw(stage - lo, row offset, value).
+// gradients of its stages (sweep 0) through gw(stage - lo, register, row
+// offset, value).
 template <class P, int g, bool TOPPRIOR, bool ZTOP, class Sink>
 __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
@@ -289,7 +290,7 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
         if constexpr (ZTOP && sl == r - 1) {
             // a zero adjoint on the prior-topped stage: zero weight gradients
             // and nothing flows on (its R side is the prior)
-            sfor<0, ROWS>([&](auto i) { gw(sl, GMap<P, g>::off(i), 0.f); });
+            sfor<0, ROWS>([&](auto i) { gw(sl, (int)i, GMap<P, g>::off(i), 0.f); });
             return;
         }
         float go[ROWS];
@@ -308,8 +309,8 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
                 else { l1 = lbot[i]; l2 = lbot[ip]; }
                 // outputs: L'1 = w1 ms(l1, l2 + r2), L'2 = w2 ms(r1, l1) + l2
                 const float a = l2 + r2;
-                gw(sl, GMap<P, g>::off(i), go[i] * ms0c(l1, a));
-                gw(sl, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
+                gw(sl, (int)i, GMap<P, g>::off(i), go[i] * ms0c(l1, a));
+                gw(sl, ip, GMap<P, g>::off(ip), go[ip] * ms0c(l1, r1));
                 const float d1 = go[i] * wv[i], d2 = go[ip] * wv[ip];
                 const bool c1 = __builtin_fabsf(l1) <= __builtin_fabsf(a);
                 const bool c2 = __builtin_fabsf(r1) <= __builtin_fabsf(l1);
@@ -696,7 +697,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                                                 : buf + 4 * N + (g & 1) * RHO * N + base;
                         constexpr int SLS = WAVE ? 2 * N : N;
                         rev_group_R<P, g, g == 0>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                          wt + base, [&](int sl, int off, float v) { gws[sl * SLS + off] = v; });
+                                          wt + base, [&](int sl, int, int off, float v) { gws[sl * SLS + off] = v; });
                         if constexpr (g < G - 1) {
                             float *dst = buf + ((g + 1) & 1) * N;
                             sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
@@ -722,7 +723,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                 if (active) {
                     const int base = GMap<P, g>::base(t);
                     float gt[ROWS];
-                    auto sink = [&](int sl, int off, float v) { gws[sl * SLS + base + off] = v; };
+                    auto sink = [&](int sl, int, int off, float v) { gws[sl * SLS + base + off] = v; };
                     if constexpr (g == G - 1) {
                         // the output adjoint enters at the last iteration only
                         if (lastit) {
@@ -858,12 +859,32 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     sfor<0, ROWS>([&](auto i) { baddr[i] = relabel_to_row(bb + GMap<P, GB>::off(i), e, n, LOWBITS); });
                 }
             }
-            // accumulate a weight gradient of stage lo + sl, sweep d, row base + off
-            auto sink = [&](int lo, int d, int base) {
-                return [=](int sl, int off, float v) {
-                    float *p = pt + ((lo + sl) * 2 + d) * N + base + off;
-                    *p = first ? v : *p + v;
-                };
+            // The weight gradients of one reverse step (group g, sweep d) are
+            // staged in registers and added into the partial together, and the
+            // partial's entries are loaded at the start of the step beside its
+            // other loads: one memory round trip per step, where adding each
+            // gradient as it is made waited on a load per entry.
+            struct GStep {
+                float prev[P::RMAX][ROWS], val[P::RMAX][ROWS];
+            };
+            auto gstep_load = [&](auto gc, int d, int base, GStep &s) {
+                constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
+                if (!first) {
+                    sfor<0, r>([&](auto sl) {
+                        sfor<0, ROWS>([&](auto i) { s.prev[sl][i] = pt[((lo + sl) * 2 + d) * N + base + GMap<P, g>::off(i)]; });
+                    });
+                } else {
+                    sfor<0, r>([&](auto sl) { sfor<0, ROWS>([&](auto i) { s.prev[sl][i] = 0.f; }); });
+                }
+            };
+            auto gstep_store = [&](auto gc, int d, int base, const GStep &s) {
+                constexpr int g = decltype(gc)::value, r = P::size(g), lo = P::lo(g);
+                sfor<0, r>([&](auto sl) {
+                    sfor<0, ROWS>([&](auto i) {
+                        float *p = pt + ((lo + sl) * 2 + d) * N + base + GMap<P, g>::off(i);
+                        *p = first ? s.val[sl][i] : s.prev[sl][i] + s.val[sl][i];
+                    });
+                });
             };
             auto load_state = [&](auto gc, float (&rint)[RI][ROWS], float (&rtop)[ROWS]) {
                 constexpr int g = decltype(gc)::value;
@@ -981,6 +1002,8 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     const int base = GMap<P, g>::base(t);
                     float lbot[ROWS], lint[RI][ROWS], rsw[RI][ROWS], rtsw[ROWS], gsi[RI][ROWS], gst[ROWS];
                     float gli[RI][ROWS], glb[ROWS], gb[ROWS], gtop[ROWS];
+                    GStep gs;
+                    gstep_load(g, 1, base, gs);
                     load2(LS, g, lint, lbot);
                     if constexpr (g == 0) {
                         sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { rsw[l][i] = h0_rsw[l][i]; }); });
@@ -1007,7 +1030,8 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { gli[l][i] = 0.f; }); });
                     sfor<0, ROWS>([&](auto i) { glb[i] = 0.f; });
                     rev_group_R<P, g, g == 0>(lbot, lint, rsw, rtsw, gb, gsi, gli, glb, gtop, wt + base,
-                                      sink(P::lo(g), 1, base));
+                                              [&](int sl, int i, int, float v) { gs.val[sl][i] = v; });
+                    gstep_store(g, 1, base, gs);
                     if constexpr (g == G - 1) {
                         sfor<0, RI>([&](auto l) { sfor<0, ROWS>([&](auto i) { hg_gli[l][i] = gli[l][i]; }); });
                         sfor<0, ROWS>([&](auto i) { hg_glb[i] = glb[i]; });
@@ -1032,6 +1056,9 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                 const int base = GMap<P, g>::base(t);
                 float lbot[ROWS], lint[RI][ROWS], rint[RI][ROWS], rtop[ROWS], gli[RI][ROWS], glb[ROWS];
                 float gsi[RI][ROWS], gst[ROWS], gt[ROWS];
+                GStep gs;
+                gstep_load(std::integral_constant<int, g>{}, 0, base, gs);
+                auto sink = [&](int sl, int i, int, float v) { gs.val[sl][i] = v; };
                 load2(LS, std::integral_constant<int, g>{}, lint, lbot);
                 load_state(std::integral_constant<int, g>{}, rint, rtop);
                 if (lastit) {
@@ -1050,17 +1077,18 @@ __global__ void __launch_bounds__(1 << (NLOG - 2)) k_wbp_bwd_big(WbpArgs a) {
                     if (lastit) {
                         sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
                         rev_group_L<P, g, true, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
-                                                       sink(P::lo(g), 0, base));
+                                                       sink);
                     } else {
                         rev_group_L<P, g, true, true>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
-                                                      sink(P::lo(g), 0, base));
+                                                      sink);
                     }
                 } else {
                     const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
                     rev_group_L<P, g, false, false>(lbot, lint, rint, rtop, gt, gli, glb, gsi, gst, wt + base,
-                                                    sink(P::lo(g), 0, base));
+                                                    sink);
                 }
+                gstep_store(std::integral_constant<int, g>{}, 0, base, gs);
                 store2(GS, std::integral_constant<int, g>{}, gsi, gst);
                 if constexpr (g > 0) {
                     float *dst = buf + 2 * N + (g & 1) * N;
