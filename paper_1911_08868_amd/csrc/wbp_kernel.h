@@ -144,18 +144,37 @@ struct RState {
 // ---- forward passes with weights -------------------------------------------
 // wg points at the weights of this iteration, offset by the thread's row base
 // of group g; weight of stage-local sl, sweep d, register i:
-// wg[((lo + sl) * 2 + d) * N + off(i)]
+// wg[((lo + sl) * 2 + d) * N + off(i)].  The group passes also take the
+// group's weights already in registers, w[sl][i] (WgroupW, from wload), so
+// that a kernel can load them a step ahead.
+template <class P>
+using WgroupW = float[P::RMAX][P::ROWS];
+
 template <class P, int g>
+__device__ __forceinline__ void wload(const float *wg, int d, WgroupW<P> &w) {
+    sfor<0, P::size(g)>([&](auto sl) {
+        sfor<0, P::ROWS>([&](auto i) { w[sl][i] = wg[((P::lo(g) + sl) * 2 + d) * P::N + GMap<P, g>::off(i)]; });
+    });
+}
+
+template <class P, int g, int D, class WG>
+__device__ __forceinline__ float wget(const WG &wg, int sl, int i) {
+    if constexpr (std::is_pointer_v<WG>)
+        return wg[((P::lo(g) + sl) * 2 + D) * P::N + GMap<P, g>::off(i)];
+    else
+        return wg[sl][i];
+}
+template <class P, int g, class WG>
 __device__ __forceinline__ void wgroup_L(const float (&lbot)[P::ROWS], float (&lint)[P::RI][P::ROWS],
                                          const float (&rint)[P::RI][P::ROWS],
                                          const float (&rtop)[P::ROWS], float (&out)[P::ROWS],
-                                         const float *wg) {
+                                         const WG &wg) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     float cur[ROWS];
     sfor<0, ROWS>([&](auto i) { cur[i] = lbot[i]; });
     sfor<0, r>([&](auto sl) {
         float wv[ROWS];
-        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 0) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) { wv[i] = wget<P, g, 0>(wg, sl, i); });
         float nxt[ROWS];
         sfor<0, ROWS>([&](auto i) {
             constexpr int b = 1 << sl;
@@ -175,17 +194,17 @@ __device__ __forceinline__ void wgroup_L(const float (&lbot)[P::ROWS], float (&l
     sfor<0, ROWS>([&](auto i) { out[i] = cur[i]; });
 }
 
-template <class P, int g>
+template <class P, int g, class WG>
 __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                          float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
-                                         float (&out)[P::ROWS], const float *wg) {
+                                         float (&out)[P::ROWS], const WG &wg) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     float cur[ROWS];
     sfor<0, ROWS>([&](auto i) { cur[i] = rtop[i]; });
     sfor<0, r>([&](auto k) {
         constexpr int sl = r - 1 - k;
         float wv[ROWS];
-        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 1) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) { wv[i] = wget<P, g, 1>(wg, sl, i); });
         float nxt[ROWS];
         sfor<0, ROWS>([&](auto i) {
             constexpr int b = 1 << sl;
@@ -216,12 +235,12 @@ __device__ __forceinline__ void wgroup_R(const float (&lbot)[P::ROWS], const flo
 // gw(stage - lo, register, row offset, value).  The derivative routing is the
 // min-sum rule of the forward's check function, written branch-free: a select
 // per route and the sign flips as bit operations.
-template <class P, int g, bool ZBOT, class Sink>
+template <class P, int g, bool ZBOT, class WG, class Sink>
 __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rsw)[P::RI][P::ROWS], const float (&rtopsw)[P::ROWS],
                                             const float (&gbot)[P::ROWS], const float (&gstate)[P::RI][P::ROWS],
                                             float (&glint)[P::RI][P::ROWS], float (&glbot)[P::ROWS],
-                                            float (&gtop)[P::ROWS], const float *wg, Sink &&gw) {
+                                            float (&gtop)[P::ROWS], const WG &wg, Sink &&gw) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     float gacc[P::RI][ROWS];
     sfor<0, r - 1>([&](auto l) { sfor<0, ROWS>([&](auto i) { gacc[l][i] = gstate[l][i]; }); });
@@ -239,7 +258,7 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
         if constexpr (sl == 0) sfor<0, ROWS>([&](auto i) { go[i] = gbot[i]; });
         else sfor<0, ROWS>([&](auto i) { go[i] = gacc[sl - 1][i]; });
         float wv[ROWS];
-        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 1) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) { wv[i] = wget<P, g, 1>(wg, sl, i); });
         sfor<0, ROWS>([&](auto i) {
             constexpr int b = 1 << sl;
             if constexpr ((i & b) == 0) {
@@ -277,12 +296,12 @@ __device__ __forceinline__ void rev_group_R(const float (&lbot)[P::ROWS], const 
 // once; gstop untouched when the top level is the prior), stages the weight
 // gradients of its stages (sweep 0) through gw(stage - lo, register, row
 // offset, value).
-template <class P, int g, bool TOPPRIOR, bool ZTOP, class Sink>
+template <class P, int g, bool TOPPRIOR, bool ZTOP, class WG, class Sink>
 __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const float (&lint)[P::RI][P::ROWS],
                                             const float (&rint)[P::RI][P::ROWS], const float (&rtop)[P::ROWS],
                                             const float (&gtop)[P::ROWS], float (&glint)[P::RI][P::ROWS],
                                             float (&glbot)[P::ROWS], float (&gsint)[P::RI][P::ROWS],
-                                            float (&gstop)[P::ROWS], const float *wg, Sink &&gw) {
+                                            float (&gstop)[P::ROWS], const WG &wg, Sink &&gw) {
     constexpr int r = P::size(g), lo = P::lo(g), N = P::N, ROWS = P::ROWS;
     static_assert(!ZTOP || TOPPRIOR, "a zero top adjoint is the last group's");
     sfor<0, r>([&](auto k) {
@@ -297,7 +316,7 @@ __device__ __forceinline__ void rev_group_L(const float (&lbot)[P::ROWS], const 
         if constexpr (sl == r - 1) sfor<0, ROWS>([&](auto i) { go[i] = gtop[i]; });
         else sfor<0, ROWS>([&](auto i) { go[i] = glint[sl][i]; });
         float wv[ROWS];
-        sfor<0, ROWS>([&](auto i) { wv[i] = wg[((lo + sl) * 2 + 0) * N + GMap<P, g>::off(i)]; });
+        sfor<0, ROWS>([&](auto i) { wv[i] = wget<P, g, 0>(wg, sl, i); });
         sfor<0, ROWS>([&](auto i) {
             constexpr int b = 1 << sl;
             if constexpr ((i & b) == 0) {
@@ -494,6 +513,9 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     float Rsw[G][RI][ROWS], Rtsw[G][ROWS];  // R messages of this iteration's R sweep
     float gsi[G][RI][ROWS], gst[G][ROWS];   // adjoint of the R state leaving the iteration
     float gli[G][RI][ROWS], glb[G][ROWS];   // adjoints of the L messages
+    WgroupW<P> wc, wn;                      // weights of the current and the next group step
+    sfor<0, P::RMAX>([&](auto l) { sfor<0, ROWS>([&](auto i) { wc[l][i] = 0.f; wn[l][i] = 0.f; }); });
+    static_assert(G >= 2, "the step order below assumes two groups or more");
     int baddr[ROWS], toprow[ROWS];
     uint32_t frozen_bits = 0;
     auto order_at = [&](int it) { return (KP > 0 && a.Q > 1) ? (it / a.Tev) % a.Q : 0; };
@@ -622,8 +644,28 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     });
                 }
             }
+            // One-wave frames load each group step's weights one step ahead
+            // (into wn, while the step before computes; wc holds the current
+            // step's): steps that loaded their own waited on the L2, with two
+            // waves per SIMD to hide it.  Longer frames, whose registers the
+            // second set would cost occupancy, load each step's own (wown).
+            constexpr bool WPF = WAVE;
+            auto wnext = [&](auto gc, int d) {
+                constexpr int g = decltype(gc)::value;
+                if constexpr (WPF) wload<P, g>(wt + GMap<P, g>::base(t), d, wn);
+            };
+            auto wshift = [&]() {
+                if constexpr (WPF)
+                    sfor<0, P::RMAX>([&](auto l) { sfor<0, ROWS>([&](auto i) { wc[l][i] = wn[l][i]; }); });
+            };
+            auto wown = [&](auto gc, int d) {
+                constexpr int g = decltype(gc)::value;
+                if constexpr (!WPF) wload<P, g>(wt + GMap<P, g>::base(t), d, wc);
+            };
             // ---- recompute the L sweep ----
+            if constexpr (WPF) wload<P, 0>(wt + GMap<P, 0>::base(t), 0, wc);
             sfor<0, G - 1>([&](auto g) {
+                wnext(std::integral_constant<int, g + 1>{}, 0);
                 if (active) {
                     const int base = GMap<P, g>::base(t);
                     if constexpr (g > 0) {
@@ -632,14 +674,18 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                         else sfor<0, ROWS>([&](auto i) { st.Lbot[g][i] = lb[base + GMap<P, g>::off(i)]; });
                     }
                     float out[ROWS];
-                    wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
+                    wown(g, 0);
+                    wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wc);
                     float *lt = buf + ((g + 1) & 1) * N;
                     sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
                 }
                 boundary_sync<WAVE>();
+                wshift();
             });
             float prior[ROWS];
             sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
+            // next: the R sweep's first step, or the reverse L sweep's (the same group)
+            wnext(std::integral_constant<int, G - 1>{}, lastit ? 0 : 1);
             if (active) {
                 const int base = GMap<P, G - 1>::base(t);
                 if constexpr (G > 1) {
@@ -647,29 +693,40 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
                     else sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
                 }
-                wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
-                // ---- recompute the R sweep, keeping every level ----
-                if (!lastit) {
+                wown(std::integral_constant<int, G - 1>{}, 0);
+                wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wc);
+            }
+            wshift();
+            // ---- recompute the R sweep, keeping every level ----
+            if (!lastit) {
+                wnext(std::integral_constant<int, G - 2>{}, 1);
+                if (active) {
+                    const int base = GMap<P, G - 1>::base(t);
                     sfor<0, ROWS>([&](auto i) { Rtsw[G - 1][i] = prior[i]; });
                     float rb[ROWS];
-                    wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], Rsw[G - 1], prior, rb, wt + base);
+                    wown(std::integral_constant<int, G - 1>{}, 1);
+                    wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], Rsw[G - 1], prior, rb, wc);
                     if constexpr (G > 1) {
                         float *rt = buf + 2 * N + ((G - 1) & 1) * N;
                         if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
                         else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
                     }
                 }
+                wshift();
             }
             boundary_sync<WAVE>();
             if (!lastit) {
                 sfor<0, G - 1>([&](auto k) {
                     constexpr int g = G - 2 - k;
+                    // next: group g - 1; after group 0 the reverse R sweep starts on group 0
+                    if constexpr (g > 0) wnext(std::integral_constant<int, g - 1>{}, 1);
                     if (active) {
                         const int base = GMap<P, g>::base(t);
                         const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { Rtsw[g][i] = rs[base + GMap<P, g>::off(i)]; });
                         float rb[ROWS];
-                        wgroup_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], rb, wt + base);
+                        wown(std::integral_constant<int, g>{}, 1);
+                        wgroup_R<P, g>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], rb, wc);
                         if constexpr (g > 0) {
                             float *rt = buf + 2 * N + (g & 1) * N;
                             if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
@@ -677,9 +734,13 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                         }
                     }
                     boundary_sync<WAVE>();
+                    if constexpr (g > 0) wshift();
                 });
                 // ---- reverse of the R sweep: groups bottom to top ----
                 sfor<0, G>([&](auto g) {
+                    // next: group g + 1, or after the last the reverse L sweep's first
+                    if constexpr (g + 1 < G) wnext(std::integral_constant<int, g + 1>{}, 1);
+                    else wnext(std::integral_constant<int, G - 1>{}, 0);
                     if constexpr (g > 0 && !WAVE) flush(std::integral_constant<int, g - 1>{}, 1, (g - 1) & 1, it);
                     if (active) {
                         const int base = GMap<P, g>::base(t);
@@ -696,14 +757,16 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                         float *const gws = WAVE ? buf + 4 * N + (P::lo(g) * 2 + 1) * N + base
                                                 : buf + 4 * N + (g & 1) * RHO * N + base;
                         constexpr int SLS = WAVE ? 2 * N : N;
+                        wown(g, 1);
                         rev_group_R<P, g, g == 0>(st.Lbot[g], st.Lint[g], Rsw[g], Rtsw[g], gb, gsi[g], gli[g], glb[g], gtop,
-                                          wt + base, [&](int sl, int, int off, float v) { gws[sl * SLS + off] = v; });
+                                          wc, [&](int sl, int, int off, float v) { gws[sl * SLS + off] = v; });
                         if constexpr (g < G - 1) {
                             float *dst = buf + ((g + 1) & 1) * N;
                             sfor<0, ROWS>([&](auto i) { dst[base + GMap<P, g>::off(i)] = gtop[i] + gst[g][i]; });
                         }
                     }
                     boundary_sync<WAVE>();
+                    wshift();
                 });
             }
             // ---- reverse of the L sweep: groups top to bottom (it writes the new
@@ -711,6 +774,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
             const int step0 = lastit ? 0 : G;  // reverse steps already taken in this iteration
             sfor<0, G>([&](auto k) {
                 constexpr int g = G - 1 - k;
+                if constexpr (g > 0) wnext(std::integral_constant<int, g - 1>{}, 0);
                 if constexpr (!WAVE) {
                     if constexpr (k == 0) {
                         if (!lastit) flush(std::integral_constant<int, G - 1>{}, 1, (G - 1) & 1, it);
@@ -724,21 +788,22 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     const int base = GMap<P, g>::base(t);
                     float gt[ROWS];
                     auto sink = [&](int sl, int, int off, float v) { gws[sl * SLS + base + off] = v; };
+                    wown(std::integral_constant<int, g>{}, 0);
                     if constexpr (g == G - 1) {
                         // the output adjoint enters at the last iteration only
                         if (lastit) {
                             sfor<0, ROWS>([&](auto i) { gt[i] = a.gout[frame * N + toprow[i]]; });
                             rev_group_L<P, g, true, false>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
-                                                           gsi[g], gst[g], wt + base, sink);
+                                                           gsi[g], gst[g], wc, sink);
                         } else {
                             rev_group_L<P, g, true, true>(st.Lbot[g], st.Lint[g], st.Rint[g], prior, gt, gli[g], glb[g],
-                                                          gsi[g], gst[g], wt + base, sink);
+                                                          gsi[g], gst[g], wc, sink);
                         }
                     } else {
                         const float *src = buf + 2 * N + ((g + 1) & 1) * N;
                         sfor<0, ROWS>([&](auto i) { gt[i] = src[base + GMap<P, g>::off(i)]; });
                         rev_group_L<P, g, false, false>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], gt, gli[g],
-                                                        glb[g], gsi[g], gst[g], wt + base, sink);
+                                                        glb[g], gsi[g], gst[g], wc, sink);
                     }
                     if constexpr (g > 0) {
                         float *dst = buf + 2 * N + (g & 1) * N;
@@ -747,6 +812,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     }
                 }
                 boundary_sync<WAVE>();
+                if constexpr (g > 0) wshift();
             });
             if constexpr (WAVE) {
                 __syncthreads();
