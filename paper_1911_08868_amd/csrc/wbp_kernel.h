@@ -528,6 +528,21 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
     // thread (16-byte LDS reads and global accesses); others take the general
     // loop.  Both add the slots in slot order.
     constexpr int SC = wbp_bwd_slots<NLOG, RHO>();
+    // a full workgroup's flush of one iteration's partial (one-wave frames):
+    // FV float4 entries, FPER per thread.  Without a permuted range each
+    // thread loads their old values at the start of the iteration, to be
+    // added at its end (it reads back only what it wrote); with one, the row
+    // maps leave no registers to hold them, and the flush loads them itself
+    constexpr int FV = n * 2 * N / 4, FB = SC * TPS, FPER = (FV + FB - 1) / FB;
+    constexpr bool FPF = WAVE && KP == 0;
+    float4 fold[FPER];
+    auto fold_load = [&](int it) {
+        const float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
+        sfor<0, FPER>([&](auto k) {
+            const int i4 = tid + k * FB;
+            if (FV % FB == 0 || i4 < FV) fold[k] = *reinterpret_cast<const float4 *>(part + 4 * i4);
+        });
+    };
     for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
         const bool first = bt == (int64_t)blockIdx.x;  // the partial's first batch stores
         const int64_t frame0 = bt * S, frame = frame0 + slot;
@@ -548,7 +563,7 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
         auto put1 = [&](float *p, float v) { *p = first ? v : *p + v; };
         auto flush_all = [&](int it, bool lastit) {
             float *part = a.partial + ((int64_t)blockIdx.x * a.T + it) * (int64_t)n * 2 * N;
-            if (full) {
+            if (full && !FPF) {
                 for (int i4 = tid; i4 < n * 2 * N / 4; i4 += blockDim.x) {
                     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (!(lastit && (((4 * i4) / N) & 1))) {
@@ -560,6 +575,28 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
                     put4(part + 4 * i4, v);
                 }
                 return;
+            }
+            if constexpr (FPF) {
+                if (full) {
+                    sfor<0, FPER>([&](auto k) {
+                        const int i4 = tid + k * FB;
+                        if (FV % FB == 0 || i4 < FV) {
+                            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                            if (!(lastit && (((4 * i4) / N) & 1))) {
+                                sfor<0, SC>([&](auto sc) {
+                                    const float4 w = *reinterpret_cast<const float4 *>(smem + (size_t)sc * PS + 4 * N + 4 * i4);
+                                    v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+                                });
+                            }
+                            if (!first) {
+                                const float4 o = fold[k];
+                                v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+                            }
+                            *reinterpret_cast<float4 *>(part + 4 * i4) = v;
+                        }
+                    });
+                    return;
+                }
             }
             for (int idx = tid; idx < n * 2 * N; idx += blockDim.x) {
                 float v = 0.f;
@@ -597,6 +634,9 @@ __global__ void __launch_bounds__((wbp_bwd_launch_bound<NLOG, RHO>())) k_wbp_bwd
             const int q = order_at(it);
             const float *wt = a.w + (int64_t)it * n * 2 * N;
             const bool lastit = (it == a.T - 1);
+            if constexpr (FPF) {
+                if (full && !first) fold_load(it);
+            }
             if (active) {
                 const int8_t *e = ords + q * 16;
                 const int base = GMap<P, G - 1>::base(t);
