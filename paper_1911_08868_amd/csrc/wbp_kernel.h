@@ -396,6 +396,15 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
     });
     if (active) maps(0);
 
+    // each group step's weights, loaded into registers before its pass
+    // (loaded one step ahead, as the one-wave adjoint does, they gained
+    // nothing here)
+    WgroupW<P> wc;
+    auto wown = [&](auto gc, const float *wtp, int d) {
+        constexpr int g = decltype(gc)::value;
+        wload<P, g>(wtp + GMap<P, g>::base(t), d, wc);
+    };
+
     for (int it = 0; it < a.T; ++it) {
         if constexpr (KP > 0) {
             if (it == next_ev) {  // trellis event: the next order of the pool
@@ -434,35 +443,34 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                 }
                 float out[ROWS];
                 const int base = GMap<P, g>::base(t);
-                wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wt + base);
+                wown(g, wt, 0);
+                wgroup_L<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], out, wc);
                 float *lt = buf + ((g + 1) & 1) * N;
                 sfor<0, ROWS>([&](auto i) { lt[base + GMap<P, g>::off(i)] = out[i]; });
             }
             boundary_sync<WAVE>();
         });
+        static_assert(G >= 2, "the step order below assumes two groups or more");
+        float prior[ROWS];
+        sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
+        const int btop = GMap<P, G - 1>::base(t);
         if (active) {
-            if constexpr (G > 1) {
-                const float *lb = buf + ((G - 1) & 1) * N;
-                if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
-                else {
-                    const int base = GMap<P, G - 1>::base(t);
-                    sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[base + GMap<P, G - 1>::off(i)]; });
-                }
-            }
-            float prior[ROWS];
-            sfor<0, ROWS>([&](auto i) { prior[i] = ((frozen_bits >> i) & 1u) ? kWbpPrior : 0.f; });
-            const int base = GMap<P, G - 1>::base(t);
-            wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wt + base);
-            if (it == a.T - 1) {
+            const float *lb = buf + ((G - 1) & 1) * N;
+            if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[baddr[i]]; });
+            else sfor<0, ROWS>([&](auto i) { st.Lbot[G - 1][i] = lb[btop + GMap<P, G - 1>::off(i)]; });
+            wown(std::integral_constant<int, G - 1>{}, wt, 0);
+            wgroup_L<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, st.Ltop, wc);
+            if (it == a.T - 1)
                 sfor<0, ROWS>([&](auto i) { a.out[frame * N + toprow[i]] = st.Ltop[i] + prior[i]; });
-            } else {
+        }
+        if (it < a.T - 1) {
+            if (active) {
                 float rb[ROWS];
-                wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, rb, wt + base);
-                if constexpr (G > 1) {
-                    float *rt = buf + 2 * N + ((G - 1) & 1) * N;
-                    if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
-                    else sfor<0, ROWS>([&](auto i) { rt[base + GMap<P, G - 1>::off(i)] = rb[i]; });
-                }
+                wown(std::integral_constant<int, G - 1>{}, wt, 1);
+                wgroup_R<P, G - 1>(st.Lbot[G - 1], st.Lint[G - 1], st.Rint[G - 1], prior, rb, wc);
+                float *rt = buf + 2 * N + ((G - 1) & 1) * N;
+                if constexpr (MAPPED && G - 1 == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
+                else sfor<0, ROWS>([&](auto i) { rt[btop + GMap<P, G - 1>::off(i)] = rb[i]; });
             }
         }
         boundary_sync<WAVE>();
@@ -474,7 +482,8 @@ __global__ void __launch_bounds__((wbp_launch_bound<NLOG, RHO>())) k_wbp_fwd(Wbp
                 const float *rs = buf + 2 * N + ((g + 1) & 1) * N;
                 sfor<0, ROWS>([&](auto i) { st.Rtop[g][i] = rs[base + GMap<P, g>::off(i)]; });
                 float rb[ROWS];
-                wgroup_R<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], rb, wt + base);
+                wown(std::integral_constant<int, g>{}, wt, 1);
+                wgroup_R<P, g>(st.Lbot[g], st.Lint[g], st.Rint[g], st.Rtop[g], rb, wc);
                 if constexpr (g > 0) {
                     float *rt = buf + 2 * N + (g & 1) * N;
                     if constexpr (MAPPED && g == GB) sfor<0, ROWS>([&](auto i) { rt[baddr[i]] = rb[i]; });
