@@ -215,20 +215,27 @@ def test_weighted_large_frames_more_than_the_grid(orc, pbp, N, K, T, F, pp):
     assert np.array_equal(gw.view(np.uint32), again.view(np.uint32))
 
 
-@pytest.mark.parametrize("N,K,T,F", [(64, 32, 3, 32 * 300 + 5), (16, 8, 2, 128 * 270 + 3),
-                                     (256, 144, 3, 8 * 300 + 3), (1024, 512, 2, 600)])
-def test_weighted_gradient_over_many_workgroups(orc, pbp, N, K, T, F):
+@pytest.mark.parametrize("N,K,T,F,pp", [(64, 32, 3, 32 * 300 + 5, None), (16, 8, 2, 128 * 270 + 3, None),
+                                        (256, 144, 3, 8 * 300 + 3, None), (1024, 512, 2, 600, None),
+                                        (256, 144, 4, 8 * 300 + 5, (4, 1, 8)), (1024, 512, 3, 520, (5, 2, 4))])
+def test_weighted_gradient_over_many_workgroups(orc, pbp, N, K, T, F, pp):
     # more batches of frames than the adjoint's fixed grid (256 workgroups up
     # to N = 256, 512 above): the first workgroups take a second batch and add
     # into their partial, the last batch is ragged, and more than 64 partials
-    # take both levels of the gradient reduction
+    # take both levels of the gradient reduction; with the permuted range the
+    # one-wave adjoint takes its other flush (the partial loaded at the flush)
     n = N.bit_length() - 1
     oc, u, llr = _setup(orc, N, K, F, seed=3 + F)
     rng = np.random.default_rng(F)
     w = rng.uniform(0.7, 1.3, (T, n, 2, N)).astype(np.float32).astype(np.float64)
     gout = rng.normal(size=(F, N)).astype(np.float32).astype(np.float64)
-    out, gw = _gpu(pbp, oc, llr, w, T, None, gout)
-    opp = orc.WbpParams(fp32=True)
+    if pp:
+        k, tev, Q = pp
+        opp = orc.WbpParams(pp_mode=orc.PP_LASTK, k=k, T_ev=tev, Q=Q, seed=9, fp32=True)
+        gpp = pbp.PPParams(mode=pbp.PP_LASTK, k=k, period_T=tev, pool_Q=Q, seed=9)
+    else:
+        opp, gpp = orc.WbpParams(fp32=True), None
+    out, gw = _gpu(pbp, oc, llr, w, T, gpp, gout)
     assert np.array_equal(out.view(np.uint32), orc.wbp_forward(oc, llr, w, opp).astype(np.float32).view(np.uint32))
     ref_gw, _, absum = orc.wbp_backward(oc, llr, w, opp, gout, want_abs=True)
     _check_grad(gw, ref_gw, absum, F)
